@@ -1,0 +1,206 @@
+/* liblq: lattice Dirac-operator solvers for AMD MI355X (gfx950).
+ *
+ * The calls follow the problem statement of arXiv:2201.09004 ("Performance
+ * of the GPU inverters with Chroma+QUDA for various fermion actions"):
+ * compute a propagator, i.e. solve D(U; m, omega, c_sw) x = b column by column
+ * (12 spin-colour columns for Wilson-type actions, sec. 2.1 and Table 2;
+ * 3 colour columns for staggered, sec. 2.2 and Table 3) to a stated
+ * residual, for the twisted-mass clover (sec. 2.1, eqs. 1-3), HISQ staggered
+ * (sec. 2.2, eq. 4) and overlap (sec. 2.3, eq. 5 and the sign-function form
+ * that follows it) actions.
+ *
+ * Conventions (shared by every entry point):
+ *   - extents L = {Lx, Ly, Lz, Lt}, all even (>= 4 for HISQ so that the
+ *     three-hop Naik term does not alias); site s = x + Lx*(y + Ly*(z + Lz*t));
+ *     mu = 0..3 is x, y, z, t; parity = (x+y+z+t) & 1, even = 0.
+ *   - gauge links: [V][4][3][3] complex128 (re, im interleaved), U_mu(x)[row][col]
+ *     the link from x to x + mu.  Space is periodic; with t_antiperiodic the
+ *     library applies the fermion time-boundary sign itself.
+ *   - Wilson-type fields: [n_rhs][V][4][3] complex128 (spin, colour), chiral
+ *     gamma basis gamma_k = [[0, -i sigma_k], [i sigma_k, 0]],
+ *     gamma_4 = [[0, 1], [1, 0]], gamma_5 = diag(1, 1, -1, -1).
+ *   - staggered fields: [n_rhs][V][3] complex128.  HISQ fat (one-hop) and long
+ *     (three-hop) links are passed with smearing and Naik coefficients
+ *     absorbed and WITHOUT staggered phases; the library applies the MILC
+ *     phases eta_t = 1, eta_x = (-1)^t, eta_y = (-1)^(t+x), eta_z = (-1)^(t+x+y).
+ *
+ * Operators (kind and op codes below):
+ *   D_W(m)  = (4+m) - 1/2 sum_mu [(1-g_mu) U_mu(x) d_{x+mu} + (1+g_mu) U^dag_mu(x-mu) d_{x-mu}]
+ *             (eq. 2 read with the standard sign; eq. 2 as printed is -g5 D_W g5)
+ *   TM-clover D = D_W(m) + C + i mu g5, C = -(c_sw/2) sum_{mu<nu} g_mu g_nu F_mu_nu
+ *             (eq. 1 with omega = m + i mu on i g5, eq. 3 with the Luescher normalisation)
+ *   HISQ     D = m + 1/2 sum_mu eta_mu [V d_{+mu} - V^dag d_{-mu} + W d_{+3mu} - W^dag d_{-3mu}]
+ *   overlap  D(m) = (rho - m/2)(1 + g5 eps(H_W)) + m, H_W = g5 D_W(-rho),
+ *             eps(H) v ~= H sum_{k=0}^{N} c_k T_k(Z) v, Z = (2 H^2 - (a+b))/(b-a),
+ *             evaluated by Clenshaw's recursion (sec. 2.3, Fig. 2).
+ *
+ * Errors: every call returns lq_status (0 = LQ_OK, negative on error) and
+ * never aborts; lq_last_error() gives a message for the calling thread.
+ * Ownership: host pointers are borrowed for the duration of the call and
+ * copied; lq_field handles belong to the library until lq_field_free; the
+ * _dev variants borrow caller device memory (same canonical layouts, FP64)
+ * and enqueue on the caller's HIP stream, returning after the work is
+ * enqueued and the stats are final (they synchronise that stream).
+ */
+#ifndef LQ_H
+#define LQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LQ_OK = 0,
+  LQ_EINVAL = -1,     /* bad argument: odd extent, unknown kind/op, bad sizes, NULL pointer */
+  LQ_ENOMEM = -2,     /* device allocation failed (or server budget exceeded) */
+  LQ_EDEVICE = -3,    /* HIP runtime error */
+  LQ_ENOCONV = -4,    /* maxiter reached; x holds the best iterate, stats are filled */
+  LQ_EBREAKDOWN = -5, /* BiCGStab breakdown that a restart did not cure */
+  LQ_ENUMERIC = -6,   /* NaN or Inf in a reduction */
+  LQ_EBUSY = -7,      /* server: request not finished / queue full */
+  LQ_ENOTSUP = -8     /* combination not supported (e.g. FP16 with clover) */
+} lq_status;
+
+typedef struct lq_ctx lq_ctx;
+typedef struct lq_field lq_field;
+typedef struct lq_server lq_server;
+
+typedef struct {
+  int32_t L[4];           /* Lx, Ly, Lz, Lt: all even */
+  int32_t t_antiperiodic; /* 1: antiperiodic fermion time boundary (default) */
+} lq_geom;
+
+enum { LQ_WILSON = 0, LQ_TM_CLOVER = 1, LQ_HISQ = 2, LQ_OVERLAP = 3 };
+
+typedef struct {
+  int32_t kind;       /* LQ_WILSON, LQ_TM_CLOVER, LQ_HISQ, LQ_OVERLAP */
+  double m;           /* Wilson/TM mass m of D_W(m) (Re omega); HISQ mass; overlap quark mass */
+  double mu;          /* twisted mass (Im omega), TM only */
+  double c_sw;        /* clover coefficient, TM only (0: no clover term) */
+  double rho;         /* overlap: D_W(-rho) kernel, rho ~ 1.5 */
+  int32_t cheb_N;     /* overlap: polynomial order in H^2 (2N+1 H_W products) */
+  double cheb_a;      /* overlap: interval [a, b] holding the spectrum of H_W^2 */
+  double cheb_b;      /*   (both 0: the library measures it, see lq_hw_bounds) */
+  const double *cheb_c; /* overlap: N+1 coefficients (host), or NULL: the library
+                           interpolates y^(-1/2) at the Chebyshev nodes of [a,b] */
+} lq_action;
+
+/* operator selector for lq_apply (the result is written for every site of
+ * `out` that the operator defines; other sites are set to zero) */
+enum {
+  LQ_OP_D = 0,         /* full-lattice D of the action */
+  LQ_OP_DDAG = 1,      /* D^dag */
+  LQ_OP_HOP = 2,       /* hopping part: Wilson -1/2 sum(...), HISQ D - m */
+  LQ_OP_SITE = 3,      /* TM: site term A = (4+m) + C + i mu g5 */
+  LQ_OP_SITE_INV = 4,  /* TM: A^{-1} */
+  LQ_OP_SCHUR = 5,     /* TM: M_hat = 1 - A_ee^-1 D_eo A_oo^-1 D_oe on even sites */
+  LQ_OP_HW = 6,        /* overlap: H_W = g5 D_W(-rho) */
+  LQ_OP_SIGN = 7,      /* overlap: eps_N(H_W) */
+  LQ_OP_NORMAL_EVEN = 8 /* HISQ: M_e(m) = m^2 - D_eo D_oe on even sites */
+};
+
+typedef struct {
+  double tol;              /* target relative true residual ||b - D x|| / ||b|| (FP64) */
+  int32_t maxiter;         /* iteration cap of the main Krylov loop (0: 10000) */
+  int32_t sloppy_bits;     /* 64, 32 or 16: storage of the inner iterations */
+  double reliable_delta;   /* reliable update when ||r|| < delta * max ||r|| since the last one (0: 0.1) */
+  int32_t n_shift;         /* HISQ multi-shift: number of masses (0 or 1: single mass = action.m) */
+  const double *masses;    /* HISQ multi-shift: n_shift masses (host) */
+  int32_t reconstruct_full;/* HISQ: 1 returns x_i = D(m_i)^dag y_i on all sites, 0 returns y_i on even sites */
+  int32_t recon12;         /* 1: 12-real link reconstruction in sloppy FP32/FP16 Wilson stencils */
+  int32_t use_initial_guess;/* 1: x holds the initial guess on input */
+  int32_t fault_inject;    /* testing: 1 NaN in the first reduction, 2 allocation failure, 3 maxiter=1 */
+  int32_t solver;          /* 0: default for the action, 1: CG on normal equations (full lattice) */
+} lq_params;
+
+typedef struct {
+  int32_t iters;           /* Krylov iterations of the main loop (max over columns) */
+  int32_t reliable_updates;
+  double true_rel_res;     /* max over columns (and shifts) of the FP64 relative true residual */
+  double seconds;          /* wall time of the call */
+  double gflops;           /* stencil flops / seconds / 1e9 (standard per-site counts) */
+  double hbm_bytes;        /* compulsory HBM bytes of the stencil applications */
+  int32_t status;
+  int32_t n_apply;         /* stencil (half-)applications issued */
+} lq_stats;
+
+/* Context on one device.  `device` is the HIP device ordinal. */
+lq_status lq_init(int device, lq_ctx **ctx);
+lq_status lq_finalize(lq_ctx *ctx);
+/* Message of the last failed call on this thread (static storage, valid until the next call). */
+const char *lq_last_error(void);
+/* Library version string. */
+const char *lq_version(void);
+
+/* Gauge field for Wilson-type actions.  U: host [V][4][3][3] complex128 (SU(3)
+ * for the 12-real reconstruction).  The clover term is built on the device
+ * from U when an action with c_sw != 0 first needs it (sec. 2.1: the clover
+ * term and its twisted inverse are computed on the GPU). */
+lq_status lq_gauge_load(lq_ctx *ctx, const lq_geom *geom, const double *U, lq_field **g);
+lq_status lq_gauge_load_dev(lq_ctx *ctx, const lq_geom *geom, const double *U_dev, void *stream, lq_field **g);
+/* HISQ fat (one-hop) and long (three-hop) links, host [V][4][3][3] complex128 each. */
+lq_status lq_hisq_load(lq_ctx *ctx, const lq_geom *geom, const double *fat, const double *lng, lq_field **g);
+lq_status lq_hisq_load_dev(lq_ctx *ctx, const lq_geom *geom, const double *fat_dev, const double *lng_dev,
+                           void *stream, lq_field **g);
+lq_status lq_field_free(lq_field *g);
+
+/* Apply one operator (op codes above) once to n_rhs columns, with field
+ * storage of prec_bits = 64, 32 or 16 (FP16: values scaled by a per-site FP32
+ * norm, FP32 accumulation), optionally OR-ed with LQ_PREC_RECON12 (FP32/FP16
+ * Wilson-type links stored as two rows, the third rebuilt as conj(r0 x r1)).
+ * in/out: canonical layouts, n_rhs columns (n_rhs = 0 is a no-op). */
+#define LQ_PREC_RECON12 0x100
+lq_status lq_apply(lq_ctx *ctx, const lq_action *act, const lq_field *g, int op, int prec_bits, int n_rhs,
+                   const double *in, double *out);
+lq_status lq_apply_dev(lq_ctx *ctx, const lq_action *act, const lq_field *g, int op, int prec_bits, int n_rhs,
+                       const double *in_dev, double *out_dev, void *stream);
+
+/* Solve D x = b for n_rhs columns to prm->tol relative true residual.
+ *   LQ_WILSON:     CG on D^dag D (full lattice)
+ *   LQ_TM_CLOVER:  even-odd (symmetric Schur) BiCGStab, sloppy storage + FP64 reliable updates
+ *   LQ_HISQ:       multi-shift CG on M_e(m_i) = m_i^2 - D_eo D_oe (even sites), then a
+ *                  per-shift mixed-precision CG refinement; x is [n_shift][n_rhs][V][3]
+ *   LQ_OVERLAP:    CG on D(m)^dag D(m) with FP64 vectors, sloppy sign function and FP64
+ *                  reliable updates.
+ * x: on input the initial guess if prm->use_initial_guess, on output the solution.
+ * stats may be NULL. */
+lq_status lq_solve(lq_ctx *ctx, const lq_action *act, const lq_field *g, const lq_params *prm, int n_rhs,
+                   const double *b, double *x, lq_stats *stats);
+lq_status lq_solve_dev(lq_ctx *ctx, const lq_action *act, const lq_field *g, const lq_params *prm, int n_rhs,
+                       const double *b_dev, double *x_dev, lq_stats *stats, void *stream);
+
+/* Extremal |eigenvalues| of H_W = g5 D_W(-rho) by FP64 Lanczos on H_W^2 (sec. 2.3:
+ * the Chebyshev interval must hold the spectrum). */
+lq_status lq_hw_bounds(lq_ctx *ctx, const lq_action *act, const lq_field *g, int iters, double *lmin,
+                       double *lmax);
+/* Coefficients c_0..c_N of the Chebyshev interpolant of y^(-1/2) on [a, b] (host, FP64). */
+lq_status lq_cheb_coeffs(double a, double b, int N, double *c);
+
+/* Kernel timing with HIP events on the stream each kernel is launched on.
+ * enable=1 clears and starts recording; lq_profile_get returns, for kernel
+ * family `name` ("wilson", "stag", "blas", ...), the launch count and the
+ * average duration in milliseconds. */
+lq_status lq_profile(lq_ctx *ctx, int enable);
+lq_status lq_profile_get(lq_ctx *ctx, const char *name, int64_t *count, double *avg_ms);
+
+/* Serving: continuous batching of solves that share (field, action, params)
+ * into one multi-RHS batch, admission by HBM footprint, resident gauge fields.
+ * A request is n_rhs columns; columns join and leave the running batch at
+ * iteration boundaries.  b and x are host buffers owned by the caller until
+ * the request completes; stats may be NULL. */
+lq_status lq_server_create(lq_ctx *ctx, size_t hbm_budget, int max_cols, lq_server **srv);
+lq_status lq_server_destroy(lq_server *srv);
+lq_status lq_submit(lq_server *srv, const lq_action *act, const lq_field *g, const lq_params *prm, int n_rhs,
+                    const double *b, double *x, lq_stats *stats, uint64_t *ticket);
+lq_status lq_poll(lq_server *srv, uint64_t ticket, int *done);
+lq_status lq_wait(lq_server *srv, uint64_t ticket);
+lq_status lq_server_stats(lq_server *srv, double *p50_s, double *p99_s, double *solves_per_s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LQ_H */

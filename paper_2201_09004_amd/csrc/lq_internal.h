@@ -1,0 +1,182 @@
+// Host-side objects of liblq: context, fields, device vectors, kernel timing,
+// and the operator / solver entry points used by the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lq.h"
+#include "lq_kernels.h"
+
+namespace lq {
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+inline int pidx(int prec) { return prec == 64 ? 0 : prec == 32 ? 1 : 2; }
+
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+
+}  // namespace lq
+
+struct lq_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;  // stream of the host-pointer API
+  bool prof = false;
+  std::vector<lq::ProfRec> pending;
+  std::vector<hipEvent_t> event_pool;
+  std::map<std::string, std::pair<int64_t, double>> totals;
+  double* partial = nullptr;  // reduction partials
+  size_t partial_bytes = 0;
+  std::mutex mtx;
+};
+
+namespace lq {
+
+struct Clover {
+  void* H[2] = {nullptr, nullptr};     // [FP64, FP32] packed Hermitian (4+m)+C
+  void* Ainv[2] = {nullptr, nullptr};  // [FP64, FP32] full complex (H +- i mu)^{-1}
+};
+
+}  // namespace lq
+
+struct lq_field {
+  lq_ctx* ctx = nullptr;
+  int type = 0;  // 0 Wilson gauge, 1 HISQ
+  lq::Geom g{};
+  double* aos = nullptr;   // canonical FP64 copy (gauge / fat)
+  double* aos2 = nullptr;  // long links
+  void* links[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  void* fat[3] = {nullptr, nullptr, nullptr};
+  void* lng[3] = {nullptr, nullptr, nullptr};
+  float sfat[3] = {1, 1, 1}, slng[3] = {1, 1, 1};
+  std::map<std::tuple<double, double, double>, lq::Clover> clover;
+  std::mutex mtx;
+};
+
+namespace lq {
+
+// ------------------------------------------------------------------ timing
+struct Prof {
+  lq_ctx* c;
+  hipStream_t s;
+  int idx = -1;
+  Prof(lq_ctx* ctx, const char* name, hipStream_t st);
+  ~Prof();
+};
+void prof_flush(lq_ctx* c);
+
+// ------------------------------------------------------------------ vectors
+// A set of ncol columns of one field type (nc = 12 Wilson, 3 staggered) and
+// precision, storing npar parities per column (npar = 1: parity `par0` only).
+struct Vec {
+  FieldRef f{};
+  int prec = 64, nc = 12, ncol = 0, npar = 2, par0 = 0;
+  size_t bytes = 0;
+  hipStream_t s = nullptr;
+  bool owner = true;
+  Vec() = default;
+  Vec(const Vec&) = delete;
+  Vec& operator=(const Vec&) = delete;
+  Vec(Vec&& o) noexcept { *this = std::move(o); }
+  Vec& operator=(Vec&& o) noexcept;
+  ~Vec();
+  bool ok() const { return f.data != nullptr || ncol == 0; }
+  // view of columns [c0, c0+n)
+  FieldRef cols(int c0) const;
+};
+Vec make_vec(const Geom& g, int prec, int nc, int ncol, int npar, int par0, hipStream_t s);
+Vec view(const Vec& v, int c0, int n);  // non-owning view of columns [c0, c0+n)
+int vec_zero(Vec& v);
+int vec_copy(Vec& dst, const Vec& src);  // with precision conversion, same shape
+
+// scoped device buffer
+struct DBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  hipStream_t s = nullptr;
+  DBuf() = default;
+  DBuf(size_t bytes, hipStream_t st);
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      if (p) hipFreeAsync(p, s);
+      p = o.p;
+      n = o.n;
+      s = o.s;
+      o.p = nullptr;
+    }
+    return *this;
+  }
+  ~DBuf();
+  template <typename T> T* as() const { return (T*)p; }
+};
+
+// ------------------------------------------------------------------ operators
+struct OpEnv {
+  lq_ctx* ctx;
+  lq_field* f;
+  lq_action act;
+  hipStream_t s;
+  int recon = 0;
+  std::vector<double> cheb;  // Chebyshev coefficients (overlap)
+  double a = 0, b = 0;
+  int64_t n_apply = 0;       // stencil half-applications (counted per parity)
+  double flops = 0, bytes = 0;
+};
+
+int ensure_links(OpEnv& e, int prec);
+int ensure_clover(OpEnv& e, int prec);
+const Clover* get_clover(OpEnv& e);
+
+// Wilson-type: full-lattice D, D^dag, hop; site terms; Schur operator and helpers
+int wilson_D(OpEnv& e, int prec, Vec& out, const Vec& in, bool dag);
+int wilson_hop(OpEnv& e, int prec, Vec& out, const Vec& in);
+int tm_site(OpEnv& e, int prec, Vec& out, const Vec& in, bool inverse);
+int tm_schur(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o);
+int tm_schur_source(OpEnv& e, Vec& bhat_e, const Vec& b);                 // FP64
+int tm_schur_reconstruct(OpEnv& e, Vec& x, const Vec& x_e, const Vec& b); // FP64, x full
+// overlap
+int hw_apply(OpEnv& e, int prec, Vec& out, const Vec& in);
+int sign_apply(OpEnv& e, int prec, Vec& out, const Vec& in);
+int overlap_D(OpEnv& e, int prec, Vec& out, const Vec& in, bool dag);
+int overlap_prepare(OpEnv& e);
+// staggered
+int stag_D(OpEnv& e, int prec, Vec& out, const Vec& in, bool dag, const double* acol_dev = nullptr);
+int stag_hop(OpEnv& e, int prec, Vec& out, const Vec& in);
+int stag_normal_even(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o, const double* acol_dev, double a);
+
+// ------------------------------------------------------------------ BLAS helpers
+struct Blas {
+  lq_ctx* ctx = nullptr;
+  hipStream_t s = nullptr;
+  int gridx = 1;
+  double* partial = nullptr;  // owned by `part`, sized for the columns given to blas_prepare
+  DBuf part;
+  int op(int opc, Vec* f0, Vec* f1 = nullptr, Vec* f2 = nullptr, Vec* f3 = nullptr, Vec* f4 = nullptr,
+         const double* st = nullptr, int c0 = 0, int c1 = 0);
+  int opi(int opc, Vec* f0, Vec* f1, Vec* f2, double c0re, double c0im = 0, double c1re = 0, double c1im = 0);
+};
+int blas_prepare(lq_ctx* c, Blas& b, const Geom& g, int npar, int ncol, hipStream_t s);
+
+int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, int n_rhs, const double* b_dev,
+          double* x_dev, lq_stats* st, hipStream_t s);
+int apply_op(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec, int n_rhs, const double* in_dev,
+             double* out_dev, hipStream_t s);
+int hw_bounds(lq_ctx* c, const lq_action* act, lq_field* f, int iters, double* lmin, double* lmax, hipStream_t s);
+void cheb_coeffs(double a, double b, int N, double* c);
+
+}  // namespace lq

@@ -1,0 +1,128 @@
+// Kernel launch descriptors and launchers of liblq (host-callable, defined in
+// the .hip files).  Every launcher enqueues on the given stream and returns 0,
+// or a negative status when the launch itself fails.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lq_common.h"
+
+namespace lq {
+
+// ------------------------------------------------------------ Wilson type
+enum { EPI_HOP = 0, EPI_XPAY, EPI_XPAY_G5, EPI_CLOVINV, EPI_XMY_CLOVINV, EPI_SITE, EPI_CHEB };
+
+struct WilsonArgs {
+  Geom g;
+  int prec, recon, dag, epi;
+  int par_out;  // 0, 1, or 2 = both parities
+  int ncol, block;
+  const void* links;
+  FieldRef in, out, x, v, b1, b2;
+  const void* clov;      // packed Hermitian H = (4+m) + C per chirality
+  const void* clov_inv;  // full complex A^{-1} per chirality
+  const double* acol;    // per-column coefficient of x (or nullptr: use a)
+  double a, k_hop, mu_tw, s1, ck, s2;
+};
+int launch_wilson(const WilsonArgs& A, hipStream_t s);
+
+// site term of the twisted-clover operator: out = A x or A^{-1} x per site
+int launch_site(const Geom& g, int prec, const void* clov, const void* clov_inv, double mu_tw, bool inverse,
+                FieldRef in, FieldRef out, int par_out, int ncol, hipStream_t s);
+
+// ------------------------------------------------------------ staggered
+enum { SEPI_HOP = 0, SEPI_XPAY };
+
+struct StagArgs {
+  Geom g;
+  int prec, epi, par_out, ncol, block;
+  const void* fat;
+  const void* lng;
+  float sfat, slong;
+  FieldRef in, out, x;
+  const double* acol;
+  double a, k_hop;
+};
+int launch_stag(const StagArgs& A, hipStream_t s);
+
+// ------------------------------------------------------------ packing
+// canonical AoS (device, FP64 complex): gauge [V][4][3][3]; spinor [col][V][NC]
+int launch_pack_links(const Geom& g, const double* aos, void* out, int prec, int ne, int hisq_phases,
+                      double scale, hipStream_t s);
+int launch_pack_field(const Geom& g, const double* aos, int ncol, int nc, FieldRef out, int prec, int par_sel,
+                      hipStream_t s);
+int launch_unpack_field(const Geom& g, FieldRef in, int prec, int ncol, int nc, double* aos, int par_sel,
+                        hipStream_t s);
+int launch_convert(FieldRef dst, int pdst, FieldRef src, int psrc, int nc, int ncol, int npar, int Vh,
+                   hipStream_t s);
+double link_maxabs(const double* aos, int64_t n, hipStream_t s);
+
+// ------------------------------------------------------------ clover (FP64 build)
+int launch_clover_build(const Geom& g, const void* links64, double csw, double m, double mu, void* H64,
+                        void* Ainv64, hipStream_t s);
+int launch_clover_convert(const void* src64, void* dst32, int64_t n_t2, hipStream_t s);
+
+// ------------------------------------------------------------ BLAS / reductions
+enum {
+  OP_AXPY = 0,   // f1 += c0 * f0
+  OP_AXMY,       // f1 -= c0 * f0
+  OP_XPAY,       // f1 = f0 + c0 * f1
+  OP_CG,         // f2 += c0 f0 ; f3 -= c0 f1 ; red |f3|^2
+  OP_BICG_XR,    // f3 += c0 f0 + c1 f1 ; f1 = f1 - c1 f2 ; red <f4,f1>, |f1|^2   (c0=alpha, c1=omega)
+  OP_BICG_P,     // f2 = f0 + c0 (f2 - c1 f1)                                     (c0=beta, c1=omega)
+  OP_DOT,        // red <f0, f1>
+  OP_NORM2,      // red |f0|^2
+  OP_DOT_NORM,   // red <f0, f1>, |f0|^2
+  OP_XMY_NORM,   // f1 = f0 - f1 ; red |f1|^2
+  OP_ZERO,       // f0 = 0
+  OP_SCALE,      // f0 *= c0
+  OP_G5,         // f1 = g5 f0 (Wilson only)
+  OP_LC_G5,      // f2 = c0 f0 + c1 g5 f1 (Wilson only)
+  OP_COPY,       // f1 = f0
+  OP_NCOUNT
+};
+
+constexpr int ST_STRIDE = 16;  // doubles of solver state per column
+enum { ST_RHO = 0, ST_ALPHA = 2, ST_OMEGA = 4, ST_BETA = 6, ST_RR = 8, ST_FLAG = 9, ST_ACTIVE = 10, ST_AUX = 11,
+       ST_RR0 = 13, ST_PAD = 14 };
+
+struct BlasArgs {
+  int prec, nc, ncol, npar, Vh, op;
+  FieldRef f[5];
+  const double* st;  // solver state [col][ST_STRIDE]; nullptr: use imm
+  int c0, c1;        // offsets of complex coefficients in the state
+  double imm[4];     // immediate coefficients c0 = imm[0] + i imm[1], c1 = imm[2] + i imm[3]
+  double* partial;   // [ncol][gridx][4]
+  int gridx;
+};
+int launch_blas(const BlasArgs& A, hipStream_t s);
+int blas_gridx(int64_t nsite);
+
+// y(prec_y) += x(prec_x) element-wise, both with the same shape
+int launch_axpy_mixed(FieldRef y, int py, FieldRef x, int px, int nc, int ncol, int npar, int Vh, hipStream_t s);
+
+// scalar recurrences
+enum { SC_CG_ALPHA = 0, SC_CG_BETA, SC_BICG_ALPHA, SC_BICG_OMEGA, SC_BICG_BETA, SC_SET_RR, SC_SET_RHO_RR,
+       SC_DOT_TO_AUX };
+int launch_scalar(int op, const double* partial, int gridx, int ncol, double* st, hipStream_t s);
+
+// multi-shift CG (Jegerlehner): fields with ncol = nshift * nrhs, shift-major
+struct MsArgs {
+  int prec, nc, nrhs, nshift, npar, Vh;
+  FieldRef x, p, r, ap;
+  double* sh;  // shift state [nshift][nrhs][8]
+  double* st;  // base state [nrhs][ST_STRIDE]
+  double* partial;
+  int gridx;
+};
+int launch_ms_xr(const MsArgs& A, hipStream_t s);     // x_i += a_i p_i ; r -= a Ap ; red |r|^2
+int launch_ms_p(const MsArgs& A, hipStream_t s);      // p_0 = r + b p_0 ; p_i = z_i r + b_i p_i
+int launch_ms_scalar_alpha(const MsArgs& A, const double* sigma, hipStream_t s);
+int launch_ms_scalar_beta(const MsArgs& A, hipStream_t s);
+int launch_ms_init(const MsArgs& A, hipStream_t s);
+
+// profiling-free utilities
+int launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace lq

@@ -1,0 +1,638 @@
+// Operators of the four actions composed from the stencil, site and BLAS
+// kernels: Wilson and twisted-clover D (sec. 2.1), the even-odd Schur
+// complement, H_W and the Chebyshev/Clenshaw sign function with the overlap
+// operator (sec. 2.3), and the HISQ staggered operator with its even-site
+// normal operator (sec. 2.2).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "lq_internal.h"
+
+namespace lq {
+
+// ------------------------------------------------------------------ timing
+Prof::Prof(lq_ctx* ctx, const char* name, hipStream_t st) : c(ctx), s(st) {
+  if (!c || !c->prof) return;
+  hipEvent_t ev[2];
+  for (int k = 0; k < 2; ++k) {
+    if (!c->event_pool.empty()) {
+      ev[k] = c->event_pool.back();
+      c->event_pool.pop_back();
+    } else {
+      hipEventCreate(&ev[k]);
+    }
+  }
+  hipEventRecord(ev[0], s);
+  c->pending.push_back({name, ev[0], ev[1]});
+  idx = (int)c->pending.size() - 1;
+}
+Prof::~Prof() {
+  if (idx < 0) return;
+  hipEventRecord(c->pending[idx].b, s);
+  if (c->pending.size() > 8192) prof_flush(c);
+}
+void prof_flush(lq_ctx* c) {
+  for (auto& r : c->pending) {
+    hipEventSynchronize(r.b);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, r.a, r.b);
+    auto& t = c->totals[r.name];
+    t.first += 1;
+    t.second += ms;
+    c->event_pool.push_back(r.a);
+    c->event_pool.push_back(r.b);
+  }
+  c->pending.clear();
+}
+
+// ------------------------------------------------------------------ vectors
+static size_t block_bytes(int prec, int nc, int Vh) { return (size_t)site_bytes(prec, nc) * Vh; }
+
+Vec make_vec(const Geom& g, int prec, int nc, int ncol, int npar, int par0, hipStream_t s) {
+  Vec v;
+  v.prec = prec;
+  v.nc = nc;
+  v.ncol = ncol;
+  v.npar = npar;
+  v.par0 = par0;
+  v.s = s;
+  const size_t nblk = (size_t)ncol * npar;
+  const size_t main = nblk * block_bytes(prec, nc, g.Vh);
+  const size_t nb = prec == 16 ? nblk * g.Vh * sizeof(float) : 0;
+  const size_t mainr = (main + 255) / 256 * 256;
+  v.bytes = mainr + nb;
+  v.f.npar = npar;
+  v.f.Vh = g.Vh;
+  if (ncol == 0) return v;
+  void* p = nullptr;
+  if (hipMallocAsync(&p, v.bytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return v;
+  }
+  v.f.data = p;
+  v.f.norm = prec == 16 ? (float*)((char*)p + mainr) : nullptr;
+  return v;
+}
+
+Vec& Vec::operator=(Vec&& o) noexcept {
+  if (this != &o) {
+    if (f.data && owner) hipFreeAsync(f.data, s);
+    f = o.f;
+    prec = o.prec;
+    nc = o.nc;
+    ncol = o.ncol;
+    npar = o.npar;
+    par0 = o.par0;
+    bytes = o.bytes;
+    s = o.s;
+    owner = o.owner;
+    o.f.data = nullptr;
+    o.f.norm = nullptr;
+  }
+  return *this;
+}
+Vec::~Vec() {
+  if (f.data && owner) hipFreeAsync(f.data, s);
+}
+Vec view(const Vec& v, int c0, int n) {
+  Vec r;
+  r.f = v.cols(c0);
+  r.prec = v.prec;
+  r.nc = v.nc;
+  r.ncol = n;
+  r.npar = v.npar;
+  r.par0 = v.par0;
+  r.s = v.s;
+  r.owner = false;
+  r.bytes = 0;
+  return r;
+}
+FieldRef Vec::cols(int c0) const {
+  FieldRef r = f;
+  const size_t nblk = (size_t)c0 * npar;
+  r.data = (char*)f.data + nblk * block_bytes(prec, nc, f.Vh);
+  if (f.norm) r.norm = f.norm + nblk * f.Vh;
+  return r;
+}
+
+int vec_zero(Vec& v) { return v.ncol ? launch_fill_zero(v.f.data, v.bytes, v.s) : 0; }
+
+int vec_copy(Vec& dst, const Vec& src) {
+  if (dst.ncol != src.ncol || dst.npar != src.npar || dst.nc != src.nc) return fail(LQ_EINVAL, "vec_copy: shape");
+  return launch_convert(dst.f, dst.prec, src.f, src.prec, src.nc, src.ncol, src.npar, src.f.Vh, dst.s);
+}
+
+DBuf::DBuf(size_t bytes, hipStream_t st) : n(bytes), s(st) {
+  if (bytes && hipMallocAsync(&p, bytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+}
+DBuf::~DBuf() {
+  if (p) hipFreeAsync(p, s);
+}
+
+// ------------------------------------------------------------------ fields
+int ensure_links(OpEnv& e, int prec) {
+  lq_field* f = e.f;
+  std::lock_guard<std::mutex> lk(f->mtx);
+  const int pi = pidx(prec);
+  const size_t esz = prec == 64 ? 16 : prec == 32 ? 8 : 4;
+  if (f->type == 0) {
+    const int rc = (e.recon && prec != 64) ? 1 : 0;
+    if (f->links[pi][rc]) return 0;
+    const int ne = rc ? 6 : 9;
+    void* p = nullptr;
+    if (hipMalloc(&p, esz * ne * 8 * (size_t)f->g.Vh) != hipSuccess) return fail(LQ_ENOMEM, "link allocation");
+    int r = launch_pack_links(f->g, f->aos, p, prec, ne, 0, 1.0, e.s);
+    if (r) return fail(LQ_EDEVICE, "pack links");
+    f->links[pi][rc] = p;
+    return 0;
+  }
+  if (f->fat[pi]) return 0;
+  double sf = 1.0, sl = 1.0;
+  if (prec == 16) {
+    const int64_t n = 2 * (int64_t)f->g.Vh * 4 * 18;
+    sf = 0.5 * link_maxabs(f->aos, n, e.s);
+    sl = 0.5 * link_maxabs(f->aos2, n, e.s);
+    if (!(sf > 0)) sf = 1.0;
+    if (!(sl > 0)) sl = 1.0;
+  }
+  void *pf = nullptr, *pl = nullptr;
+  const size_t bytes = esz * 9 * 8 * (size_t)f->g.Vh;
+  if (hipMalloc(&pf, bytes) != hipSuccess || hipMalloc(&pl, bytes) != hipSuccess)
+    return fail(LQ_ENOMEM, "HISQ link allocation");
+  if (launch_pack_links(f->g, f->aos, pf, prec, 9, 1, sf, e.s) ||
+      launch_pack_links(f->g, f->aos2, pl, prec, 9, 3, sl, e.s))
+    return fail(LQ_EDEVICE, "pack HISQ links");
+  f->fat[pi] = pf;
+  f->lng[pi] = pl;
+  f->sfat[pi] = (float)sf;
+  f->slng[pi] = (float)sl;
+  return 0;
+}
+
+int ensure_clover(OpEnv& e, int prec) {
+  if (prec == 16) return fail(LQ_ENOTSUP, "the clover term is stored in FP64 or FP32 only");
+  int r = ensure_links(e, 64);
+  if (r) return r;
+  lq_field* f = e.f;
+  std::lock_guard<std::mutex> lk(f->mtx);
+  auto key = std::make_tuple(e.act.m, e.act.c_sw, e.act.mu);
+  Clover& c = f->clover[key];
+  const size_t nH = 2 * 2 * 18 * (size_t)f->g.Vh, nA = 2 * 2 * 36 * (size_t)f->g.Vh;  // T2 elements
+  if (!c.H[0]) {
+    if (hipMalloc(&c.H[0], nH * 16) != hipSuccess || hipMalloc(&c.Ainv[0], nA * 16) != hipSuccess)
+      return fail(LQ_ENOMEM, "clover allocation");
+    if (launch_clover_build(f->g, f->links[0][0], e.act.c_sw, e.act.m, e.act.mu, c.H[0], c.Ainv[0], e.s))
+      return fail(LQ_EDEVICE, "clover build");
+  }
+  if (prec == 32 && !c.H[1]) {
+    if (hipMalloc(&c.H[1], nH * 8) != hipSuccess || hipMalloc(&c.Ainv[1], nA * 8) != hipSuccess)
+      return fail(LQ_ENOMEM, "clover allocation");
+    if (launch_clover_convert(c.H[0], c.H[1], (int64_t)nH, e.s) ||
+        launch_clover_convert(c.Ainv[0], c.Ainv[1], (int64_t)nA, e.s))
+      return fail(LQ_EDEVICE, "clover convert");
+  }
+  return 0;
+}
+
+const Clover* get_clover(OpEnv& e) {
+  auto it = e.f->clover.find(std::make_tuple(e.act.m, e.act.c_sw, e.act.mu));
+  return it == e.f->clover.end() ? nullptr : &it->second;
+}
+
+static void* links_for(OpEnv& e, int prec) { return e.f->links[pidx(prec)][(e.recon && prec != 64) ? 1 : 0]; }
+
+// per-site compulsory bytes: links read once, every field operand once
+static double wilson_bytes(int prec, int recon, int n_fields, int ncol, int clov_mats) {
+  const double r = prec == 64 ? 8 : prec == 32 ? 4 : 2;
+  const double link = 8 * (recon && prec != 64 ? 12 : 18) * r;
+  const double spin = 24 * r + (prec == 16 ? 4 : 0);
+  const double clov = clov_mats * 72 * (prec == 64 ? 8 : 4);
+  return link + clov + (double)ncol * n_fields * spin;
+}
+
+static int run_wilson(OpEnv& e, WilsonArgs& A, int n_fields, int clov_mats, int flops_extra) {
+  A.g = e.f->g;
+  A.recon = (e.recon && A.prec != 64) ? 1 : 0;
+  if (!A.links) return fail(LQ_EDEVICE, "links not packed");
+  const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
+  Prof p(e.ctx, "wilson", e.s);
+  int r = launch_wilson(A, e.s);
+  if (r) return fail(r == -1 ? LQ_ENOTSUP : LQ_EDEVICE, "wilson stencil launch");
+  e.n_apply += A.par_out == 2 ? 2 : 1;
+  e.flops += (double)nsite * A.ncol * (1320.0 + flops_extra);
+  e.bytes += (double)nsite * wilson_bytes(A.prec, A.recon, n_fields, A.ncol, clov_mats);
+  return 0;
+}
+
+// ------------------------------------------------------------------ Wilson type
+int wilson_D(OpEnv& e, int prec, Vec& out, const Vec& in, bool dag) {
+  int r = ensure_links(e, prec);
+  if (r) return r;
+  WilsonArgs A{};
+  A.prec = prec;
+  A.dag = dag;
+  A.par_out = 2;
+  A.ncol = in.ncol;
+  A.links = links_for(e, prec);
+  A.in = in.f;
+  A.out = out.f;
+  A.x = in.f;
+  A.k_hop = -0.5;
+  if (e.act.kind == LQ_TM_CLOVER) {
+    r = ensure_clover(e, prec);
+    if (r) return r;
+    A.epi = EPI_SITE;
+    A.clov = get_clover(e)->H[pidx(prec)];
+    A.mu_tw = dag ? -e.act.mu : e.act.mu;
+    return run_wilson(e, A, 3, 1, 504);
+  }
+  A.epi = EPI_XPAY;
+  A.a = 4.0 + e.act.m;
+  return run_wilson(e, A, 3, 0, 48);
+}
+
+int wilson_hop(OpEnv& e, int prec, Vec& out, const Vec& in) {
+  int r = ensure_links(e, prec);
+  if (r) return r;
+  WilsonArgs A{};
+  A.prec = prec;
+  A.par_out = 2;
+  A.ncol = in.ncol;
+  A.links = links_for(e, prec);
+  A.in = in.f;
+  A.out = out.f;
+  A.k_hop = -0.5;
+  A.epi = EPI_HOP;
+  return run_wilson(e, A, 2, 0, 0);
+}
+
+int tm_site(OpEnv& e, int prec, Vec& out, const Vec& in, bool inverse) {
+  int r = ensure_clover(e, prec);
+  if (r) return r;
+  const Clover* c = get_clover(e);
+  Prof p(e.ctx, "site", e.s);
+  r = launch_site(e.f->g, prec, c->H[pidx(prec)], c->Ainv[pidx(prec)], e.act.mu, inverse, in.f, out.f,
+                  in.npar == 2 ? 2 : in.par0, in.ncol, e.s);
+  return r ? fail(LQ_EDEVICE, "site kernel") : 0;
+}
+
+int tm_schur(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o) {
+  int r = ensure_links(e, prec);
+  if (!r) r = ensure_clover(e, prec);
+  if (r) return r;
+  const Clover* c = get_clover(e);
+  WilsonArgs A{};
+  A.prec = prec;
+  A.ncol = in_e.ncol;
+  A.links = links_for(e, prec);
+  A.k_hop = -0.5;
+  A.clov_inv = c->Ainv[pidx(prec)];
+  A.in = in_e.f;
+  A.out = tmp_o.f;
+  A.par_out = 1;
+  A.epi = EPI_CLOVINV;
+  r = run_wilson(e, A, 2, 2, 576);
+  if (r) return r;
+  A.in = tmp_o.f;
+  A.out = out_e.f;
+  A.x = in_e.f;
+  A.par_out = 0;
+  A.epi = EPI_XMY_CLOVINV;
+  return run_wilson(e, A, 3, 2, 600);
+}
+
+int tm_schur_source(OpEnv& e, Vec& bhat_e, const Vec& b) {
+  int r = ensure_links(e, 64);
+  if (!r) r = ensure_clover(e, 64);
+  if (r) return r;
+  const Clover* c = get_clover(e);
+  const Geom& g = e.f->g;
+  Vec t_o = make_vec(g, 64, 12, b.ncol, 1, 1, e.s);
+  Vec u_e = make_vec(g, 64, 12, b.ncol, 1, 0, e.s);
+  if (!t_o.ok() || !u_e.ok()) return fail(LQ_ENOMEM, "schur source buffers");
+  if (launch_site(g, 64, c->H[0], c->Ainv[0], e.act.mu, true, b.f, t_o.f, 1, b.ncol, e.s))
+    return fail(LQ_EDEVICE, "site");
+  WilsonArgs A{};
+  A.prec = 64;
+  A.ncol = b.ncol;
+  A.links = links_for(e, 64);
+  A.in = t_o.f;
+  A.out = u_e.f;
+  A.x = b.f;
+  A.a = 1.0;
+  A.k_hop = 0.5;
+  A.par_out = 0;
+  A.epi = EPI_XPAY;
+  r = run_wilson(e, A, 3, 0, 48);
+  if (r) return r;
+  if (launch_site(g, 64, c->H[0], c->Ainv[0], e.act.mu, true, u_e.f, bhat_e.f, 0, b.ncol, e.s))
+    return fail(LQ_EDEVICE, "site");
+  return 0;
+}
+
+int tm_schur_reconstruct(OpEnv& e, Vec& x, const Vec& x_e, const Vec& b) {
+  int r = ensure_links(e, 64);
+  if (!r) r = ensure_clover(e, 64);
+  if (r) return r;
+  const Clover* c = get_clover(e);
+  const Geom& g = e.f->g;
+  Vec u_o = make_vec(g, 64, 12, b.ncol, 1, 1, e.s);
+  if (!u_o.ok()) return fail(LQ_ENOMEM, "reconstruct buffers");
+  WilsonArgs A{};
+  A.prec = 64;
+  A.ncol = b.ncol;
+  A.links = links_for(e, 64);
+  // x_e into the even half of x (hop scaled by zero)
+  A.in = x_e.f;
+  A.out = x.f;
+  A.x = x_e.f;
+  A.a = 1.0;
+  A.k_hop = 0.0;
+  A.par_out = 0;
+  A.epi = EPI_XPAY;
+  r = run_wilson(e, A, 2, 0, 0);
+  if (r) return r;
+  // u_o = b_o - D_oe x_e = b_o + 1/2 hop(x_e)
+  A.out = u_o.f;
+  A.x = b.f;
+  A.k_hop = 0.5;
+  A.par_out = 1;
+  r = run_wilson(e, A, 3, 0, 48);
+  if (r) return r;
+  if (launch_site(g, 64, c->H[0], c->Ainv[0], e.act.mu, true, u_o.f, x.f, 1, b.ncol, e.s))
+    return fail(LQ_EDEVICE, "site");
+  return 0;
+}
+
+// ------------------------------------------------------------------ overlap
+int hw_apply(OpEnv& e, int prec, Vec& out, const Vec& in) {
+  int r = ensure_links(e, prec);
+  if (r) return r;
+  WilsonArgs A{};
+  A.prec = prec;
+  A.par_out = 2;
+  A.ncol = in.ncol;
+  A.links = links_for(e, prec);
+  A.in = in.f;
+  A.out = out.f;
+  A.x = in.f;
+  A.a = 4.0 - e.act.rho;
+  A.k_hop = -0.5;
+  A.epi = EPI_XPAY_G5;
+  return run_wilson(e, A, 3, 0, 48);
+}
+
+int overlap_prepare(OpEnv& e) {
+  if (!e.cheb.empty()) return 0;
+  if (e.act.cheb_N < 1) return fail(LQ_EINVAL, "overlap: cheb_N must be >= 1");
+  double a = e.act.cheb_a, b = e.act.cheb_b;
+  if (!(a > 0 && b > a)) {
+    double lmin = 0, lmax = 0;
+    int r = hw_bounds(e.ctx, &e.act, e.f, 200, &lmin, &lmax, e.s);
+    if (r) return r;
+    a = 0.9 * lmin * lmin;
+    b = 1.1 * lmax * lmax;
+  }
+  e.a = a;
+  e.b = b;
+  e.cheb.assign(e.act.cheb_N + 1, 0.0);
+  if (e.act.cheb_c) std::memcpy(e.cheb.data(), e.act.cheb_c, sizeof(double) * (e.act.cheb_N + 1));
+  else cheb_coeffs(a, b, e.act.cheb_N, e.cheb.data());
+  return 0;
+}
+
+int sign_apply(OpEnv& e, int prec, Vec& out, const Vec& in) {
+  int r = overlap_prepare(e);
+  if (!r) r = ensure_links(e, prec);
+  if (r) return r;
+  const Geom& g = e.f->g;
+  const int N = (int)e.cheb.size() - 1;
+  const double a = e.a, b = e.b;
+  Vec bk1 = make_vec(g, prec, 12, in.ncol, 2, 0, e.s);
+  Vec bk2 = make_vec(g, prec, 12, in.ncol, 2, 0, e.s);
+  Vec w = make_vec(g, prec, 12, in.ncol, 2, 0, e.s);
+  if (!bk1.ok() || !bk2.ok() || !w.ok()) return fail(LQ_ENOMEM, "sign buffers");
+  Blas bl;
+  if ((r = blas_prepare(e.ctx, bl, g, 2, in.ncol, e.s))) return r;
+  // b_N = c_N v ; b_{N+1} = 0
+  BlasArgs A{};
+  {
+    BlasArgs B{};
+    B.prec = prec; B.nc = 12; B.ncol = in.ncol; B.npar = 2; B.Vh = g.Vh; B.op = OP_LC_G5;
+    B.f[0] = in.f; B.f[1] = in.f; B.f[2] = bk1.f; B.imm[0] = e.cheb[N]; B.gridx = bl.gridx;
+    Prof p(e.ctx, "blas", e.s);
+    if (launch_blas(B, e.s)) return fail(LQ_EDEVICE, "blas");
+  }
+  if ((r = vec_zero(bk2))) return fail(LQ_EDEVICE, "zero");
+  WilsonArgs W{};
+  W.prec = prec;
+  W.par_out = 2;
+  W.ncol = in.ncol;
+  W.links = links_for(e, prec);
+  W.a = 4.0 - e.act.rho;
+  W.k_hop = -0.5;
+  W.epi = EPI_CHEB;
+  W.v = in.f;
+  for (int k = N - 1; k >= 0; --k) {
+    if ((r = hw_apply(e, prec, w, bk1))) return r;
+    W.in = w.f;
+    W.x = w.f;
+    W.b1 = bk1.f;
+    W.b2 = bk2.f;
+    W.out = bk2.f;
+    W.ck = e.cheb[k];
+    if (k > 0) {
+      W.s1 = 4.0 / (b - a);
+      W.s2 = -2.0 * (a + b) / (b - a);
+    } else {
+      W.s1 = 2.0 / (b - a);
+      W.s2 = -(a + b) / (b - a);
+    }
+    if ((r = run_wilson(e, W, 6, 0, 96))) return r;
+    std::swap(bk1, bk2);  // bk1 = b_k, bk2 = b_{k+1}
+  }
+  (void)A;
+  // bk1 now holds y = sum_k c_k T_k(Z) v
+  return hw_apply(e, prec, out, bk1);
+}
+
+int overlap_D(OpEnv& e, int prec, Vec& out, const Vec& in, bool dag) {
+  const Geom& g = e.f->g;
+  Blas bl;
+  int r = blas_prepare(e.ctx, bl, g, 2, in.ncol, e.s);
+  if (r) return r;
+  const double rho = e.act.rho, m = e.act.m;
+  Vec ein = make_vec(g, prec, 12, in.ncol, 2, 0, e.s);
+  Vec eps = make_vec(g, prec, 12, in.ncol, 2, 0, e.s);
+  if (!ein.ok() || !eps.ok()) return fail(LQ_ENOMEM, "overlap buffers");
+  const Vec* src = &in;
+  if (dag) {
+    if ((r = bl.op(OP_G5, const_cast<Vec*>(&in), &ein))) return r;
+    src = &ein;
+  }
+  if ((r = sign_apply(e, prec, eps, *src))) return r;
+  BlasArgs B{};
+  B.prec = prec; B.nc = 12; B.ncol = in.ncol; B.npar = 2; B.Vh = g.Vh; B.op = OP_LC_G5;
+  B.f[0] = src->f; B.f[1] = eps.f; B.f[2] = dag ? ein.f : out.f; B.gridx = bl.gridx;
+  B.imm[0] = rho + 0.5 * m;
+  B.imm[2] = rho - 0.5 * m;
+  {
+    Prof p(e.ctx, "blas", e.s);
+    if (launch_blas(B, e.s)) return fail(LQ_EDEVICE, "blas");
+  }
+  if (dag) return bl.op(OP_G5, &ein, &out);
+  return 0;
+}
+
+// ------------------------------------------------------------------ staggered
+static int run_stag(OpEnv& e, StagArgs& A, int n_fields) {
+  A.g = e.f->g;
+  const int pi = pidx(A.prec);
+  A.fat = e.f->fat[pi];
+  A.lng = e.f->lng[pi];
+  A.sfat = e.f->sfat[pi];
+  A.slong = e.f->slng[pi];
+  const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
+  Prof p(e.ctx, "stag", e.s);
+  if (launch_stag(A, e.s)) return fail(LQ_EDEVICE, "staggered stencil launch");
+  e.n_apply += A.par_out == 2 ? 2 : 1;
+  const double rb = A.prec == 64 ? 8 : A.prec == 32 ? 4 : 2;
+  e.flops += (double)nsite * A.ncol * 1146.0;
+  e.bytes += (double)nsite * (16 * 18 * rb + (double)A.ncol * n_fields * (6 * rb + (A.prec == 16 ? 4 : 0)));
+  return 0;
+}
+
+int stag_D(OpEnv& e, int prec, Vec& out, const Vec& in, bool dag, const double* acol_dev) {
+  int r = ensure_links(e, prec);
+  if (r) return r;
+  StagArgs A{};
+  A.prec = prec;
+  A.epi = SEPI_XPAY;
+  A.par_out = 2;
+  A.ncol = in.ncol;
+  A.in = in.f;
+  A.out = out.f;
+  A.x = in.f;
+  A.a = e.act.m;
+  A.acol = acol_dev;
+  A.k_hop = dag ? -1.0 : 1.0;
+  return run_stag(e, A, 3);
+}
+
+int stag_hop(OpEnv& e, int prec, Vec& out, const Vec& in) {
+  int r = ensure_links(e, prec);
+  if (r) return r;
+  StagArgs A{};
+  A.prec = prec;
+  A.epi = SEPI_HOP;
+  A.par_out = 2;
+  A.ncol = in.ncol;
+  A.in = in.f;
+  A.out = out.f;
+  A.k_hop = 1.0;
+  return run_stag(e, A, 2);
+}
+
+int stag_normal_even(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o, const double* acol_dev, double a) {
+  int r = ensure_links(e, prec);
+  if (r) return r;
+  StagArgs A{};
+  A.prec = prec;
+  A.ncol = in_e.ncol;
+  A.epi = SEPI_HOP;
+  A.par_out = 1;
+  A.in = in_e.f;
+  A.out = tmp_o.f;
+  A.k_hop = 1.0;
+  if ((r = run_stag(e, A, 2))) return r;
+  A.epi = SEPI_XPAY;
+  A.par_out = 0;
+  A.in = tmp_o.f;
+  A.out = out_e.f;
+  A.x = in_e.f;
+  A.acol = acol_dev;
+  A.a = a;
+  A.k_hop = -1.0;
+  return run_stag(e, A, 3);
+}
+
+// ------------------------------------------------------------------ BLAS helper
+int blas_prepare(lq_ctx* c, Blas& b, const Geom& g, int npar, int ncol, hipStream_t s) {
+  b.ctx = c;
+  b.s = s;
+  b.gridx = blas_gridx((int64_t)npar * g.Vh);
+  const size_t need = (size_t)std::max(ncol, 1) * b.gridx * 4 * sizeof(double);
+  b.part = DBuf(need, s);
+  if (!b.part.p) return fail(LQ_ENOMEM, "reduction buffer");
+  b.partial = b.part.as<double>();
+  return 0;
+}
+
+int Blas::op(int opc, Vec* f0, Vec* f1, Vec* f2, Vec* f3, Vec* f4, const double* st, int c0, int c1) {
+  BlasArgs A{};
+  A.prec = f0->prec;
+  A.nc = f0->nc;
+  A.ncol = f0->ncol;
+  A.npar = f0->npar;
+  A.Vh = f0->f.Vh;
+  A.op = opc;
+  Vec* fs[5] = {f0, f1, f2, f3, f4};
+  for (int k = 0; k < 5; ++k) {
+    if (!fs[k]) continue;
+    if (fs[k]->prec != A.prec || fs[k]->npar != A.npar || fs[k]->ncol < A.ncol)
+      return fail(LQ_EINVAL, "blas: operand shape/precision mismatch");
+    A.f[k] = fs[k]->f;
+  }
+  A.st = st;
+  A.c0 = c0;
+  A.c1 = c1;
+  A.partial = partial;
+  A.gridx = gridx;
+  Prof p(ctx, "blas", s);
+  return launch_blas(A, s) ? fail(LQ_EDEVICE, "blas launch") : 0;
+}
+
+int Blas::opi(int opc, Vec* f0, Vec* f1, Vec* f2, double c0re, double c0im, double c1re, double c1im) {
+  BlasArgs A{};
+  A.prec = f0->prec;
+  A.nc = f0->nc;
+  A.ncol = f0->ncol;
+  A.npar = f0->npar;
+  A.Vh = f0->f.Vh;
+  A.op = opc;
+  A.f[0] = f0->f;
+  if (f1) A.f[1] = f1->f;
+  if (f2) A.f[2] = f2->f;
+  A.imm[0] = c0re;
+  A.imm[1] = c0im;
+  A.imm[2] = c1re;
+  A.imm[3] = c1im;
+  A.partial = partial;
+  A.gridx = gridx;
+  Prof p(ctx, "blas", s);
+  return launch_blas(A, s) ? fail(LQ_EDEVICE, "blas launch") : 0;
+}
+
+// ------------------------------------------------------------------ Chebyshev
+void cheb_coeffs(double a, double b, int N, double* c) {
+  // interpolation of y^{-1/2} at the N+1 Chebyshev nodes of [a, b]; c_0 halved
+  const double pi = 3.14159265358979323846;
+  std::vector<double> f(N + 1), th(N + 1);
+  for (int j = 0; j <= N; ++j) {
+    th[j] = pi * (j + 0.5) / (N + 1);
+    const double y = 0.5 * (b - a) * std::cos(th[j]) + 0.5 * (b + a);
+    f[j] = 1.0 / std::sqrt(y);
+  }
+  for (int k = 0; k <= N; ++k) {
+    double s = 0.0;
+    for (int j = 0; j <= N; ++j) s += std::cos(k * th[j]) * f[j];
+    c[k] = 2.0 * s / (N + 1);
+  }
+  c[0] *= 0.5;
+}
+
+}  // namespace lq

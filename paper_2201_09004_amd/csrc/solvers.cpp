@@ -1,0 +1,735 @@
+// Krylov drivers (host control, device data and scalars):
+//   * mixed-precision CG with reliable updates (Wilson normal equations,
+//     HISQ per-shift refinement, overlap outer solve);
+//   * mixed-precision BiCGStab with reliable updates on the even-odd Schur
+//     system of the twisted-clover operator (sec. 2.1, Table 2);
+//   * multi-shift CG for several staggered masses at once (sec. 2.3 cites
+//     the shifted Krylov solvers; Table 3 uses CG for HISQ);
+//   * FP64 Lanczos for the spectral interval of H_W^2 (sec. 2.3).
+// Every solution is accepted only when its FP64 true residual, computed with
+// the FP64 operator of the full (unpreconditioned) system, meets the target.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+
+#include "lq_internal.h"
+
+namespace lq {
+
+namespace {
+
+struct HostPinned {
+  double* p = nullptr;
+  explicit HostPinned(size_t n) {
+    if (hipHostMalloc((void**)&p, n * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+  }
+  ~HostPinned() {
+    if (p) hipHostFree(p);
+  }
+};
+
+struct State {
+  DBuf dev;
+  HostPinned host;
+  int ncol;
+  hipStream_t s;
+  State(int n, hipStream_t st) : dev((size_t)std::max(n, 1) * ST_STRIDE * 8, st), host((size_t)std::max(n, 1) * ST_STRIDE), ncol(n), s(st) {}
+  bool ok() const { return dev.p && host.p; }
+  double* d() { return dev.as<double>(); }
+  double& h(int col, int k) { return host.p[col * ST_STRIDE + k]; }
+  int pull() {
+    if (hipMemcpyAsync(host.p, dev.p, (size_t)ncol * ST_STRIDE * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(LQ_EDEVICE, "state readback");
+    return 0;
+  }
+  int push() {
+    if (hipMemcpyAsync(dev.p, host.p, (size_t)ncol * ST_STRIDE * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(LQ_EDEVICE, "state upload");
+    return 0;
+  }
+};
+
+using OpFn = std::function<int(Vec& out, const Vec& in)>;
+
+struct Counters {
+  int iters = 0, reliable = 0, restarts = 0;
+  int fault = 0;
+};
+
+// per-column |v|^2 (host vector)
+int col_norms(Blas& bl, Vec& v, std::vector<double>& out) {
+  State st(v.ncol, bl.s);
+  if (!st.ok()) return fail(LQ_ENOMEM, "state");
+  int r = bl.op(OP_NORM2, &v);
+  if (r) return r;
+  if (launch_scalar(SC_SET_RR, bl.partial, bl.gridx, v.ncol, st.d(), bl.s)) return fail(LQ_EDEVICE, "scalar");
+  if ((r = st.pull())) return r;
+  out.resize(v.ncol);
+  for (int c = 0; c < v.ncol; ++c) out[c] = st.h(c, ST_RR);
+  return 0;
+}
+
+// per-column relative residual |b - A x| / |b| in FP64
+int rel_residual(Blas& bl, const OpFn& A, Vec& x, Vec& b, std::vector<double>& res, const Geom& g) {
+  Vec q = make_vec(g, 64, b.nc, b.ncol, b.npar, b.par0, bl.s);
+  if (!q.ok()) return fail(LQ_ENOMEM, "residual buffer");
+  int r = A(q, x);
+  if (r) return r;
+  if ((r = bl.op(OP_XMY_NORM, &b, &q))) return r;
+  State st(b.ncol, bl.s);
+  if (launch_scalar(SC_SET_RR, bl.partial, bl.gridx, b.ncol, st.d(), bl.s)) return fail(LQ_EDEVICE, "scalar");
+  if ((r = st.pull())) return r;
+  std::vector<double> bb;
+  if ((r = col_norms(bl, b, bb))) return r;
+  res.resize(b.ncol);
+  for (int c = 0; c < b.ncol; ++c) res[c] = bb[c] > 0 ? std::sqrt(st.h(c, ST_RR) / bb[c]) : 0.0;
+  return 0;
+}
+
+// Mixed-precision CG with reliable updates on a Hermitian positive-definite A.
+// x, b: FP64.  Columns stop when the FP64 residual of A meets tol[c] |b_c|.
+int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int plo, Vec& x, Vec& b,
+             const std::vector<double>& tol, int maxiter, double delta, Counters& cnt) {
+  const int n = b.ncol, nc = b.nc, npar = b.npar, par0 = b.par0;
+  hipStream_t s = bl.s;
+  Vec r = make_vec(g, 64, nc, n, npar, par0, s);
+  Vec q64 = make_vec(g, 64, nc, n, npar, par0, s);
+  Vec rs = make_vec(g, plo, nc, n, npar, par0, s);
+  Vec p = make_vec(g, plo, nc, n, npar, par0, s);
+  Vec q = make_vec(g, plo, nc, n, npar, par0, s);
+  Vec xs = make_vec(g, plo, nc, n, npar, par0, s);
+  State st(n, s);
+  if (!r.ok() || !q64.ok() || !rs.ok() || !p.ok() || !q.ok() || !xs.ok() || !st.ok())
+    return fail(LQ_ENOMEM, "cg buffers");
+  std::vector<double> bb;
+  int e = col_norms(bl, b, bb);
+  if (e) return e;
+  // r = b - A x (FP64)
+  auto true_res = [&]() -> int {
+    int rr = A_hi(q64, x);
+    if (rr) return rr;
+    if ((rr = bl.op(OP_XMY_NORM, &b, &q64))) return rr;
+    std::swap(r, q64);
+    if (launch_scalar(SC_SET_RR, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    return 0;
+  };
+  for (int c = 0; c < n; ++c) {
+    for (int k = 0; k < ST_STRIDE; ++k) st.h(c, k) = 0.0;
+    st.h(c, ST_ACTIVE) = 1.0;
+  }
+  if ((e = st.push())) return e;
+  if ((e = true_res())) return e;
+  if ((e = vec_copy(rs, r)) || (e = vec_copy(p, r)) || (e = vec_zero(xs))) return e ? e : fail(LQ_EDEVICE, "copy");
+  if ((e = st.pull())) return e;
+  std::vector<double> maxrr(n);
+  int nactive = 0;
+  for (int c = 0; c < n; ++c) {
+    maxrr[c] = st.h(c, ST_RR);
+    const bool act = st.h(c, ST_RR) > tol[c] * tol[c] * bb[c] && bb[c] > 0;
+    st.h(c, ST_ACTIVE) = act ? 1.0 : 0.0;
+    nactive += act;
+  }
+  if ((e = st.push())) return e;
+  bool dirty = false;  // xs holds un-folded updates
+  int it = 0;
+  for (; it < maxiter && nactive > 0; ++it) {
+    if ((e = A_lo(q, p))) return e;
+    if ((e = bl.op(OP_DOT, &p, &q))) return e;
+    if (launch_scalar(SC_CG_ALPHA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if ((e = bl.op(OP_CG, &p, &q, &xs, &rs, nullptr, st.d(), ST_ALPHA, ST_ALPHA))) return e;
+    if (launch_scalar(SC_CG_BETA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if (cnt.fault == 1 && it == 0) {
+      // injected NaN in the first reduction (host-forced test of the numeric guard)
+      if ((e = st.pull())) return e;
+      st.h(0, ST_FLAG) = 2.0;
+      if ((e = st.push())) return e;
+    }
+    dirty = true;
+    if ((e = st.pull())) return e;
+    bool update = false;
+    for (int c = 0; c < n; ++c) {
+      if (st.h(c, ST_ACTIVE) == 0.0) continue;
+      if (st.h(c, ST_FLAG) == 2.0) return fail(LQ_ENUMERIC, "NaN/Inf in a CG reduction");
+      const double rr = st.h(c, ST_RR);
+      maxrr[c] = std::max(maxrr[c], rr);
+      if (rr < delta * delta * maxrr[c] || rr < tol[c] * tol[c] * bb[c]) update = true;
+    }
+    if (update || it == maxiter - 1) {
+      ++cnt.reliable;
+      if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, n, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
+      if ((e = vec_zero(xs))) return e;
+      dirty = false;
+      // keep the CG direction scalars (beta) computed in sloppy precision
+      if ((e = true_res())) return e;
+      if ((e = vec_copy(rs, r))) return e;
+      if ((e = st.pull())) return e;
+      nactive = 0;
+      for (int c = 0; c < n; ++c) {
+        const double rr = st.h(c, ST_RR);
+        if (!std::isfinite(rr)) return fail(LQ_ENUMERIC, "NaN/Inf in the true residual");
+        maxrr[c] = rr;
+        if (st.h(c, ST_ACTIVE) != 0.0 && rr <= tol[c] * tol[c] * bb[c]) {
+          st.h(c, ST_ACTIVE) = 0.0;
+          st.h(c, ST_BETA) = 0.0;
+        }
+        nactive += st.h(c, ST_ACTIVE) != 0.0;
+      }
+      if ((e = st.push())) return e;
+    }
+    if ((e = bl.op(OP_XPAY, &rs, &p, nullptr, nullptr, nullptr, st.d(), ST_BETA, ST_BETA))) return e;
+  }
+  if (dirty) {
+    if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, n, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
+  }
+  cnt.iters += it;
+  return nactive > 0 ? LQ_ENOCONV : LQ_OK;
+}
+
+// Mixed-precision BiCGStab with reliable updates for a non-Hermitian M.
+int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int plo, Vec& x, Vec& b,
+                   const std::vector<double>& tol, int maxiter, double delta, Counters& cnt) {
+  const int n = b.ncol, nc = b.nc, npar = b.npar, par0 = b.par0;
+  hipStream_t s = bl.s;
+  Vec r = make_vec(g, 64, nc, n, npar, par0, s);
+  Vec q64 = make_vec(g, 64, nc, n, npar, par0, s);
+  Vec rs = make_vec(g, plo, nc, n, npar, par0, s);
+  Vec rhat = make_vec(g, plo, nc, n, npar, par0, s);
+  Vec p = make_vec(g, plo, nc, n, npar, par0, s);
+  Vec v = make_vec(g, plo, nc, n, npar, par0, s);
+  Vec t = make_vec(g, plo, nc, n, npar, par0, s);
+  Vec xs = make_vec(g, plo, nc, n, npar, par0, s);
+  State st(n, s);
+  if (!r.ok() || !q64.ok() || !rs.ok() || !rhat.ok() || !p.ok() || !v.ok() || !t.ok() || !xs.ok() || !st.ok())
+    return fail(LQ_ENOMEM, "bicgstab buffers");
+  std::vector<double> bb;
+  int e = col_norms(bl, b, bb);
+  if (e) return e;
+  auto true_res = [&]() -> int {
+    int rr = M_hi(q64, x);
+    if (rr) return rr;
+    if ((rr = bl.op(OP_XMY_NORM, &b, &q64))) return rr;
+    std::swap(r, q64);
+    return 0;
+  };
+  // (re)start: r = b - M x, rhat = r, p = r, rho = <rhat, r>
+  auto restart = [&]() -> int {
+    int rr = true_res();
+    if (rr) return rr;
+    if ((rr = vec_copy(rs, r)) || (rr = vec_copy(rhat, r)) || (rr = vec_copy(p, r))) return rr;
+    if ((rr = bl.op(OP_DOT_NORM, &rs, &rhat))) return rr;
+    if (launch_scalar(SC_SET_RHO_RR, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    return 0;
+  };
+  for (int c = 0; c < n; ++c) {
+    for (int k = 0; k < ST_STRIDE; ++k) st.h(c, k) = 0.0;
+    st.h(c, ST_ACTIVE) = 1.0;
+  }
+  if ((e = st.push())) return e;
+  if ((e = vec_zero(xs))) return e;
+  if ((e = restart())) return e;
+  if ((e = st.pull())) return e;
+  std::vector<double> maxrr(n);
+  int nactive = 0;
+  for (int c = 0; c < n; ++c) {
+    maxrr[c] = st.h(c, ST_RR);
+    const bool act = st.h(c, ST_RR) > tol[c] * tol[c] * bb[c] && bb[c] > 0;
+    st.h(c, ST_ACTIVE) = act ? 1.0 : 0.0;
+    nactive += act;
+  }
+  if ((e = st.push())) return e;
+  bool dirty = false;
+  int it = 0;
+  for (; it < maxiter && nactive > 0; ++it) {
+    if ((e = M_lo(v, p))) return e;
+    if ((e = bl.op(OP_DOT, &rhat, &v))) return e;
+    if (launch_scalar(SC_BICG_ALPHA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if ((e = bl.op(OP_AXMY, &v, &rs, nullptr, nullptr, nullptr, st.d(), ST_ALPHA, ST_ALPHA))) return e;
+    if ((e = M_lo(t, rs))) return e;
+    if ((e = bl.op(OP_DOT_NORM, &t, &rs))) return e;
+    if (launch_scalar(SC_BICG_OMEGA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if ((e = bl.op(OP_BICG_XR, &p, &rs, &t, &xs, &rhat, st.d(), ST_ALPHA, ST_OMEGA))) return e;
+    if (launch_scalar(SC_BICG_BETA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    dirty = true;
+    if ((e = st.pull())) return e;
+    bool update = false, breakdown = false;
+    for (int c = 0; c < n; ++c) {
+      if (st.h(c, ST_ACTIVE) == 0.0) continue;
+      if (st.h(c, ST_FLAG) == 2.0) return fail(LQ_ENUMERIC, "NaN/Inf in a BiCGStab reduction");
+      if (st.h(c, ST_FLAG) == 1.0) breakdown = true;
+      const double rr = st.h(c, ST_RR);
+      if (!std::isfinite(rr)) return fail(LQ_ENUMERIC, "NaN/Inf residual");
+      maxrr[c] = std::max(maxrr[c], rr);
+      if (rr < delta * delta * maxrr[c] || rr < tol[c] * tol[c] * bb[c]) update = true;
+    }
+    if (update || breakdown || it == maxiter - 1) {
+      ++cnt.reliable;
+      if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, n, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
+      if ((e = vec_zero(xs))) return e;
+      dirty = false;
+      if (breakdown) {
+        ++cnt.restarts;
+        if (cnt.restarts > 20) return fail(LQ_EBREAKDOWN, "BiCGStab breakdown persists after restarts");
+        for (int c = 0; c < n; ++c) st.h(c, ST_FLAG) = 0.0;
+        if ((e = st.push())) return e;
+        if ((e = restart())) return e;
+      } else {
+        if ((e = true_res())) return e;
+        if ((e = vec_copy(rs, r))) return e;
+        if ((e = bl.op(OP_DOT_NORM, &rs, &rhat))) return e;
+        if (launch_scalar(SC_SET_RHO_RR, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+      }
+      if ((e = st.pull())) return e;
+      nactive = 0;
+      for (int c = 0; c < n; ++c) {
+        const double rr = st.h(c, ST_RR);
+        maxrr[c] = rr;
+        if (st.h(c, ST_ACTIVE) != 0.0 && rr <= tol[c] * tol[c] * bb[c]) st.h(c, ST_ACTIVE) = 0.0;
+        if (st.h(c, ST_ACTIVE) == 0.0) {
+          st.h(c, ST_BETA) = st.h(c, ST_BETA + 1) = 0.0;
+          st.h(c, ST_OMEGA) = st.h(c, ST_OMEGA + 1) = 0.0;
+        }
+        nactive += st.h(c, ST_ACTIVE) != 0.0;
+      }
+      if ((e = st.push())) return e;
+      if (breakdown) continue;  // p = r already
+    }
+    if ((e = bl.op(OP_BICG_P, &rs, &v, &p, nullptr, nullptr, st.d(), ST_BETA, ST_OMEGA))) return e;
+  }
+  if (dirty) {
+    if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, n, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
+  }
+  cnt.iters += it;
+  return nactive > 0 ? LQ_ENOCONV : LQ_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ top-level solve
+int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, int n_rhs, const double* b_dev,
+          double* x_dev, lq_stats* stats, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const Geom& g = f->g;
+  OpEnv env{c, f, *act, s};
+  env.recon = prm->recon12;
+  const double tol = prm->tol > 0 ? prm->tol : 1e-10;
+  int maxiter = prm->maxiter > 0 ? prm->maxiter : 10000;
+  const double delta = prm->reliable_delta > 0 ? prm->reliable_delta : 0.1;
+  const int plo = prm->sloppy_bits == 16 ? 16 : prm->sloppy_bits == 32 ? 32 : 64;
+  Counters cnt;
+  cnt.fault = prm->fault_inject;
+  if (prm->fault_inject == 2) return fail(LQ_ENOMEM, "injected allocation failure");
+  if (prm->fault_inject == 3) maxiter = 1;
+  Blas bl;
+  int e = 0;
+  double worst = 0.0;
+  int status = LQ_OK;
+  const int kind = act->kind;
+
+  if (kind == LQ_WILSON || kind == LQ_TM_CLOVER || kind == LQ_OVERLAP) {
+    if (kind == LQ_TM_CLOVER && plo == 16) return fail(LQ_ENOTSUP, "twisted-clover sloppy storage is FP32 or FP64");
+    if (kind == LQ_OVERLAP && (e = overlap_prepare(env))) return e;
+    Vec b = make_vec(g, 64, 12, n_rhs, 2, 0, s);
+    Vec x = make_vec(g, 64, 12, n_rhs, 2, 0, s);
+    if (!b.ok() || !x.ok()) return fail(LQ_ENOMEM, "solution buffers");
+    if (launch_pack_field(g, b_dev, n_rhs, 12, b.f, 64, 2, s)) return fail(LQ_EDEVICE, "pack");
+    if (prm->use_initial_guess) {
+      if (launch_pack_field(g, x_dev, n_rhs, 12, x.f, 64, 2, s)) return fail(LQ_EDEVICE, "pack");
+    } else if ((e = vec_zero(x))) return e;
+    if ((e = blas_prepare(c, bl, g, 2, n_rhs, s))) return e;
+    OpFn D64 = [&](Vec& o, const Vec& i) {
+      if (kind == LQ_OVERLAP) return overlap_D(env, 64, o, i, false);
+      return wilson_D(env, 64, o, i, false);
+    };
+    std::vector<double> res;
+    if (kind == LQ_TM_CLOVER && prm->solver != 1) {
+      Vec bh = make_vec(g, 64, 12, n_rhs, 1, 0, s);
+      Vec xe = make_vec(g, 64, 12, n_rhs, 1, 0, s);
+      Vec to64 = make_vec(g, 64, 12, n_rhs, 1, 1, s);
+      Vec tolo = make_vec(g, plo, 12, n_rhs, 1, 1, s);
+      if (!bh.ok() || !xe.ok() || !to64.ok() || !tolo.ok()) return fail(LQ_ENOMEM, "schur buffers");
+      if ((e = tm_schur_source(env, bh, b))) return e;
+      // initial guess: even part of x
+      if (prm->use_initial_guess) {
+        // x.f blocks are [col][par]: take parity 0 of each column
+        for (int col = 0; col < n_rhs; ++col) {
+          FieldRef dst = xe.cols(col), src = x.cols(col);
+          if (launch_convert(dst, 64, src, 64, 12, 1, 1, g.Vh, s)) return fail(LQ_EDEVICE, "copy");
+        }
+      } else if ((e = vec_zero(xe))) return e;
+      Blas ble;
+      if ((e = blas_prepare(c, ble, g, 1, n_rhs, s))) return e;
+      OpFn M64 = [&](Vec& o, const Vec& i) { return tm_schur(env, 64, o, i, to64); };
+      OpFn Mlo = [&](Vec& o, const Vec& i) { return tm_schur(env, plo, o, i, tolo); };
+      std::vector<double> tol_s(n_rhs, 0.5 * tol);
+      for (int pass = 0; pass < 6; ++pass) {
+        const int rs = bicgstab_mixed(ble, g, M64, Mlo, plo, xe, bh, tol_s, maxiter, delta, cnt);
+        if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
+        if ((e = tm_schur_reconstruct(env, x, xe, b))) return e;
+        if ((e = rel_residual(bl, D64, x, b, res, g))) return e;
+        worst = *std::max_element(res.begin(), res.end());
+        status = rs;
+        if (worst <= tol || rs == LQ_ENOCONV) break;
+        for (int k = 0; k < n_rhs; ++k)
+          if (res[k] > tol) tol_s[k] *= std::max(0.05, 0.5 * tol / res[k]);
+      }
+    } else {
+      // CG on the normal equations D^dag D x = D^dag b
+      OpFn Ddag64 = [&](Vec& o, const Vec& i) {
+        if (kind == LQ_OVERLAP) return overlap_D(env, 64, o, i, true);
+        return wilson_D(env, 64, o, i, true);
+      };
+      Vec tmp64 = make_vec(g, 64, 12, n_rhs, 2, 0, s);
+      Vec tmplo = make_vec(g, plo, 12, n_rhs, 2, 0, s);
+      Vec bn = make_vec(g, 64, 12, n_rhs, 2, 0, s);
+      if (!tmp64.ok() || !tmplo.ok() || !bn.ok()) return fail(LQ_ENOMEM, "cgne buffers");
+      if ((e = Ddag64(bn, b))) return e;
+      OpFn N64 = [&](Vec& o, const Vec& i) {
+        int r = D64(tmp64, i);
+        return r ? r : Ddag64(o, tmp64);
+      };
+      OpFn Nlo = [&](Vec& o, const Vec& i) {
+        int r = kind == LQ_OVERLAP ? overlap_D(env, plo, tmplo, i, false) : wilson_D(env, plo, tmplo, i, false);
+        if (r) return r;
+        return kind == LQ_OVERLAP ? overlap_D(env, plo, o, tmplo, true) : wilson_D(env, plo, o, tmplo, true);
+      };
+      std::vector<double> tol_n(n_rhs, 0.1 * tol);
+      for (int pass = 0; pass < 6; ++pass) {
+        const int rs = cg_mixed(bl, g, N64, Nlo, plo, x, bn, tol_n, maxiter, delta, cnt);
+        if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
+        if ((e = rel_residual(bl, D64, x, b, res, g))) return e;
+        worst = *std::max_element(res.begin(), res.end());
+        status = rs;
+        if (worst <= tol || rs == LQ_ENOCONV) break;
+        for (int k = 0; k < n_rhs; ++k)
+          if (res[k] > tol) tol_n[k] *= std::max(0.01, 0.5 * tol / res[k]);
+      }
+    }
+    if (launch_unpack_field(g, x.f, 64, n_rhs, 12, x_dev, 2, s)) return fail(LQ_EDEVICE, "unpack");
+  } else if (kind == LQ_HISQ) {
+    const int nsh = prm->n_shift > 1 ? prm->n_shift : 1;
+    std::vector<double> masses(nsh, act->m);
+    if (prm->n_shift > 1) {
+      if (!prm->masses) return fail(LQ_EINVAL, "HISQ multi-shift needs masses");
+      masses.assign(prm->masses, prm->masses + nsh);
+    }
+    for (double m : masses)
+      if (!(m > 0)) return fail(LQ_EINVAL, "HISQ masses must be positive");
+    const int i0 = (int)(std::min_element(masses.begin(), masses.end()) - masses.begin());
+    const double m0 = masses[i0];
+    // shift order: base (smallest mass) first
+    std::vector<int> order;
+    order.push_back(i0);
+    for (int i = 0; i < nsh; ++i)
+      if (i != i0) order.push_back(i);
+    std::vector<double> sigma(nsh), m2col((size_t)nsh * n_rhs), mcol((size_t)nsh * n_rhs);
+    for (int k = 0; k < nsh; ++k) sigma[k] = masses[order[k]] * masses[order[k]] - m0 * m0;
+    for (int k = 0; k < nsh; ++k)
+      for (int j = 0; j < n_rhs; ++j) {
+        m2col[(size_t)k * n_rhs + j] = masses[order[k]] * masses[order[k]];
+        mcol[(size_t)k * n_rhs + j] = masses[order[k]];
+      }
+    const int ncol = nsh * n_rhs;
+    DBuf dsig(sizeof(double) * nsh, s), dm2(sizeof(double) * ncol, s), dm(sizeof(double) * ncol, s);
+    if (!dsig.p || !dm2.p || !dm.p) return fail(LQ_ENOMEM, "shift arrays");
+    hipMemcpyAsync(dsig.p, sigma.data(), sizeof(double) * nsh, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(dm2.p, m2col.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(dm.p, mcol.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, s);
+    Vec be = make_vec(g, 64, 3, n_rhs, 1, 0, s);
+    Vec brep = make_vec(g, 64, 3, ncol, 1, 0, s);
+    Vec y = make_vec(g, 64, 3, ncol, 1, 0, s);
+    if (!be.ok() || !brep.ok() || !y.ok()) return fail(LQ_ENOMEM, "HISQ buffers");
+    if (launch_pack_field(g, b_dev, n_rhs, 3, be.f, 64, 0, s)) return fail(LQ_EDEVICE, "pack");
+    for (int k = 0; k < nsh; ++k)
+      if (launch_convert(brep.cols(k * n_rhs), 64, be.f, 64, 3, n_rhs, 1, g.Vh, s)) return fail(LQ_EDEVICE, "copy");
+    Blas ble;
+    if ((e = blas_prepare(c, ble, g, 1, ncol, s))) return e;
+    if ((e = vec_zero(y))) return e;
+    if (prm->use_initial_guess) {
+      for (int k = 0; k < nsh; ++k) {
+        Vec tmp = make_vec(g, 64, 3, n_rhs, 1, 0, s);
+        if (launch_pack_field(g, x_dev + (size_t)order[k] * n_rhs * 2 * g.Vh * 3 * 2, n_rhs, 3, tmp.f, 64, 0, s))
+          return fail(LQ_EDEVICE, "pack");
+        if (launch_convert(y.cols(k * n_rhs), 64, tmp.f, 64, 3, n_rhs, 1, g.Vh, s)) return fail(LQ_EDEVICE, "copy");
+      }
+    } else if (nsh > 1) {
+      // multi-shift CG in sloppy precision to a loose tolerance, one Krylov space for all masses
+      Vec r = make_vec(g, plo, 3, n_rhs, 1, 0, s);
+      Vec ap = make_vec(g, plo, 3, n_rhs, 1, 0, s);
+      Vec to = make_vec(g, plo, 3, n_rhs, 1, 1, s);
+      Vec p = make_vec(g, plo, 3, ncol, 1, 0, s);
+      Vec xm = make_vec(g, plo, 3, ncol, 1, 0, s);
+      State st(n_rhs, s);
+      DBuf sh(sizeof(double) * 8 * ncol, s);
+      if (!r.ok() || !ap.ok() || !to.ok() || !p.ok() || !xm.ok() || !st.ok() || !sh.p)
+        return fail(LQ_ENOMEM, "multi-shift buffers");
+      if (vec_copy(r, be) || vec_zero(xm)) return fail(LQ_EDEVICE, "init");
+      for (int k = 0; k < nsh; ++k)
+        if (launch_convert(p.cols(k * n_rhs), plo, be.f, 64, 3, n_rhs, 1, g.Vh, s)) return fail(LQ_EDEVICE, "copy");
+      const double tol_ms = std::max(tol, plo == 16 ? 2e-3 : plo == 32 ? 1e-5 : tol);
+      for (int j = 0; j < n_rhs; ++j) {
+        for (int k = 0; k < ST_STRIDE; ++k) st.h(j, k) = 0.0;
+        st.h(j, ST_ACTIVE) = 1.0;
+        st.h(j, ST_PAD) = tol_ms * tol_ms;
+      }
+      if ((e = st.push())) return e;
+      Blas blr;
+      if ((e = blas_prepare(c, blr, g, 1, ncol, s))) return e;
+      MsArgs M{};
+      M.prec = plo; M.nc = 3; M.nrhs = n_rhs; M.nshift = nsh; M.npar = 1; M.Vh = g.Vh;
+      M.x = xm.f; M.p = p.f; M.r = r.f; M.ap = ap.f;
+      M.sh = sh.as<double>(); M.st = st.d(); M.partial = blr.partial; M.gridx = blr.gridx;
+      if ((e = blr.op(OP_NORM2, &r))) return e;
+      if (launch_ms_init(M, s)) return fail(LQ_EDEVICE, "ms init");
+      std::vector<double> hsh((size_t)8 * ncol);
+      Vec p0 = view(p, 0, n_rhs);
+      int it = 0;
+      for (; it < maxiter; ++it) {
+        if ((e = stag_normal_even(env, plo, ap, p0, to, nullptr, m0 * m0))) return e;
+        if ((e = blr.op(OP_DOT, &p0, &ap))) return e;
+        if (launch_ms_scalar_alpha(M, dsig.as<double>(), s)) return fail(LQ_EDEVICE, "ms alpha");
+        {
+          Prof pr(c, "blas", s);
+          if (launch_ms_xr(M, s)) return fail(LQ_EDEVICE, "ms xr");
+        }
+        if (launch_ms_scalar_beta(M, s)) return fail(LQ_EDEVICE, "ms beta");
+        {
+          Prof pr(c, "blas", s);
+          if (launch_ms_p(M, s)) return fail(LQ_EDEVICE, "ms p");
+        }
+        if ((it & 3) == 3 || it < 4) {
+          hipMemcpyAsync(hsh.data(), sh.p, sizeof(double) * 8 * ncol, hipMemcpyDeviceToHost, s);
+          if ((e = st.pull())) return e;
+          bool any = false;
+          for (int k = 0; k < ncol; ++k) any |= hsh[(size_t)k * 8 + 4] != 0.0;
+          for (int j = 0; j < n_rhs; ++j)
+            if (st.h(j, ST_FLAG) == 2.0) return fail(LQ_ENUMERIC, "NaN/Inf in multi-shift CG");
+          if (!any) break;
+        }
+      }
+      cnt.iters += it;
+      if ((e = vec_copy(y, xm))) return e;
+    }
+    // per-shift mixed-precision CG refinement on M_e(m_i) (all shifts and columns batched)
+    Vec to64 = make_vec(g, 64, 3, ncol, 1, 1, s);
+    Vec tolo = make_vec(g, plo, 3, ncol, 1, 1, s);
+    if (!to64.ok() || !tolo.ok()) return fail(LQ_ENOMEM, "HISQ buffers");
+    OpFn A64 = [&](Vec& o, const Vec& i) { return stag_normal_even(env, 64, o, i, to64, dm2.as<double>(), 0.0); };
+    OpFn Alo = [&](Vec& o, const Vec& i) { return stag_normal_even(env, plo, o, i, tolo, dm2.as<double>(), 0.0); };
+    std::vector<double> tolv(ncol, tol);
+    const int rs = cg_mixed(ble, g, A64, Alo, plo, y, brep, tolv, maxiter, delta, cnt);
+    if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
+    status = rs;
+    std::vector<double> res;
+    if ((e = rel_residual(ble, A64, y, brep, res, g))) return e;
+    worst = *std::max_element(res.begin(), res.end());
+    // output
+    const size_t colsz = (size_t)2 * g.Vh * 3 * 2;  // doubles per column
+    if (launch_fill_zero(x_dev, sizeof(double) * colsz * ncol, s)) return fail(LQ_EDEVICE, "zero");
+    Vec yo;
+    if (prm->reconstruct_full) {
+      Vec yf = make_vec(g, 64, 3, ncol, 2, 0, s);
+      yo = make_vec(g, 64, 3, ncol, 2, 0, s);
+      if (!yf.ok() || !yo.ok()) return fail(LQ_ENOMEM, "reconstruct buffers");
+      if ((e = vec_zero(yf))) return e;
+      for (int k = 0; k < ncol; ++k) {
+        FieldRef dst = yf.cols(k), src = y.cols(k);
+        if (launch_convert(dst, 64, src, 64, 3, 1, 1, g.Vh, s)) return fail(LQ_EDEVICE, "copy");
+      }
+      if ((e = stag_D(env, 64, yo, yf, true, dm.as<double>()))) return e;
+    }
+    for (int k = 0; k < nsh; ++k) {
+      double* dst = x_dev + (size_t)order[k] * n_rhs * colsz;
+      if (prm->reconstruct_full) {
+        Vec v = view(yo, k * n_rhs, n_rhs);
+        if (launch_unpack_field(g, v.f, 64, n_rhs, 3, dst, 2, s)) return fail(LQ_EDEVICE, "unpack");
+      } else {
+        Vec v = view(y, k * n_rhs, n_rhs);
+        if (launch_unpack_field(g, v.f, 64, n_rhs, 3, dst, 0, s)) return fail(LQ_EDEVICE, "unpack");
+      }
+    }
+  } else {
+    return fail(LQ_EINVAL, "unknown action kind");
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(LQ_EDEVICE, "solve synchronise");
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) {
+    stats->iters = cnt.iters;
+    stats->reliable_updates = cnt.reliable;
+    stats->true_rel_res = worst;
+    stats->seconds = secs;
+    stats->gflops = secs > 0 ? env.flops / secs * 1e-9 : 0;
+    stats->hbm_bytes = env.bytes;
+    stats->n_apply = (int32_t)std::min<int64_t>(env.n_apply, INT32_MAX);
+    stats->status = status;
+  }
+  if (status == LQ_ENOCONV) return fail(LQ_ENOCONV, "maximum iterations reached before the target residual");
+  return LQ_OK;
+}
+
+// ------------------------------------------------------------------ single application
+int apply_op(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec, int n_rhs, const double* in_dev,
+             double* out_dev, hipStream_t s) {
+  const Geom& g = f->g;
+  OpEnv env{c, f, *act, s};
+  env.recon = (prec & LQ_PREC_RECON12) ? 1 : 0;
+  prec &= ~LQ_PREC_RECON12;
+  const int kind = act->kind;
+  const int nc = kind == LQ_HISQ ? 3 : 12;
+  if ((kind == LQ_HISQ) != (f->type == 1)) return fail(LQ_EINVAL, "field type does not match the action");
+  Vec in = make_vec(g, prec, nc, n_rhs, 2, 0, s);
+  Vec out = make_vec(g, prec, nc, n_rhs, 2, 0, s);
+  if (!in.ok() || !out.ok()) return fail(LQ_ENOMEM, "apply buffers");
+  if (launch_pack_field(g, in_dev, n_rhs, nc, in.f, prec, 2, s)) return fail(LQ_EDEVICE, "pack");
+  int e = 0;
+  int par_sel = 2;
+  if (kind == LQ_HISQ) {
+    if (op == LQ_OP_D) e = stag_D(env, prec, out, in, false);
+    else if (op == LQ_OP_DDAG) e = stag_D(env, prec, out, in, true);
+    else if (op == LQ_OP_HOP) e = stag_hop(env, prec, out, in);
+    else if (op == LQ_OP_NORMAL_EVEN) {
+      Vec ie = make_vec(g, prec, 3, n_rhs, 1, 0, s), oe = make_vec(g, prec, 3, n_rhs, 1, 0, s),
+          to = make_vec(g, prec, 3, n_rhs, 1, 1, s);
+      if (!ie.ok() || !oe.ok() || !to.ok()) return fail(LQ_ENOMEM, "apply buffers");
+      if (launch_pack_field(g, in_dev, n_rhs, 3, ie.f, prec, 0, s)) return fail(LQ_EDEVICE, "pack");
+      if ((e = stag_normal_even(env, prec, oe, ie, to, nullptr, act->m * act->m))) return e;
+      if (launch_fill_zero(out_dev, sizeof(double) * 2 * 3 * 2 * (size_t)g.Vh * n_rhs, s)) return fail(LQ_EDEVICE, "zero");
+      if (launch_unpack_field(g, oe.f, prec, n_rhs, 3, out_dev, 0, s)) return fail(LQ_EDEVICE, "unpack");
+      return hipStreamSynchronize(s) == hipSuccess ? 0 : fail(LQ_EDEVICE, "sync");
+    } else return fail(LQ_EINVAL, "op not defined for HISQ");
+  } else {
+    if (kind == LQ_OVERLAP && prec == 64 && op != LQ_OP_HW && op != LQ_OP_HOP) {
+      if ((e = overlap_prepare(env))) return e;
+    }
+    switch (op) {
+      case LQ_OP_D:
+      case LQ_OP_DDAG:
+        if (kind == LQ_OVERLAP) {
+          if ((e = overlap_prepare(env))) return e;
+          e = overlap_D(env, prec, out, in, op == LQ_OP_DDAG);
+        } else {
+          e = wilson_D(env, prec, out, in, op == LQ_OP_DDAG);
+        }
+        break;
+      case LQ_OP_HOP: e = wilson_hop(env, prec, out, in); break;
+      case LQ_OP_SITE:
+      case LQ_OP_SITE_INV:
+        if (kind != LQ_TM_CLOVER) return fail(LQ_EINVAL, "site term needs the twisted-clover action");
+        e = tm_site(env, prec, out, in, op == LQ_OP_SITE_INV);
+        break;
+      case LQ_OP_SCHUR: {
+        if (kind != LQ_TM_CLOVER) return fail(LQ_EINVAL, "Schur operator needs the twisted-clover action");
+        Vec ie = make_vec(g, prec, 12, n_rhs, 1, 0, s), oe = make_vec(g, prec, 12, n_rhs, 1, 0, s),
+            to = make_vec(g, prec, 12, n_rhs, 1, 1, s);
+        if (!ie.ok() || !oe.ok() || !to.ok()) return fail(LQ_ENOMEM, "apply buffers");
+        if (launch_pack_field(g, in_dev, n_rhs, 12, ie.f, prec, 0, s)) return fail(LQ_EDEVICE, "pack");
+        if ((e = tm_schur(env, prec, oe, ie, to))) return e;
+        if (launch_fill_zero(out_dev, sizeof(double) * 2 * 12 * 2 * (size_t)g.Vh * n_rhs, s))
+          return fail(LQ_EDEVICE, "zero");
+        if (launch_unpack_field(g, oe.f, prec, n_rhs, 12, out_dev, 0, s)) return fail(LQ_EDEVICE, "unpack");
+        return hipStreamSynchronize(s) == hipSuccess ? 0 : fail(LQ_EDEVICE, "sync");
+      }
+      case LQ_OP_HW: e = hw_apply(env, prec, out, in); break;
+      case LQ_OP_SIGN:
+        if (kind != LQ_OVERLAP) return fail(LQ_EINVAL, "sign function needs the overlap action");
+        if ((e = overlap_prepare(env))) return e;
+        e = sign_apply(env, prec, out, in);
+        break;
+      default: return fail(LQ_EINVAL, "op not defined for this action");
+    }
+  }
+  if (e) return e;
+  if (launch_unpack_field(g, out.f, prec, n_rhs, nc, out_dev, par_sel, s)) return fail(LQ_EDEVICE, "unpack");
+  return hipStreamSynchronize(s) == hipSuccess ? 0 : fail(LQ_EDEVICE, "sync");
+}
+
+// ------------------------------------------------------------------ Lanczos bounds
+static void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, double& lo, double& hi) {
+  // bisection with Sturm counts on the symmetric tridiagonal (a diagonal, b off-diagonal)
+  const int n = (int)a.size();
+  double gl = 1e300, gu = -1e300;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0) + (i < n - 1 ? std::fabs(b[i]) : 0);
+    gl = std::min(gl, a[i] - r);
+    gu = std::max(gu, a[i] + r);
+  }
+  auto count = [&](double x) {
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < n; ++i) {
+      d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0) ++cnt;
+    }
+    return cnt;
+  };
+  auto kth = [&](int k) {
+    double l = gl, u = gu;
+    for (int it = 0; it < 200; ++it) {
+      const double m = 0.5 * (l + u);
+      if (count(m) > k) u = m;
+      else l = m;
+    }
+    return 0.5 * (l + u);
+  };
+  lo = kth(0);
+  hi = kth(n - 1);
+}
+
+int hw_bounds(lq_ctx* c, const lq_action* act, lq_field* f, int iters, double* lmin, double* lmax, hipStream_t s) {
+  if (f->type != 0) return fail(LQ_EINVAL, "H_W bounds need a Wilson gauge field");
+  const Geom& g = f->g;
+  OpEnv env{c, f, *act, s};
+  Blas bl;
+  int e = blas_prepare(c, bl, g, 2, 1, s);
+  if (e) return e;
+  const int64_t nd = 2 * (int64_t)g.Vh * 24;
+  std::vector<double> h(nd);
+  std::mt19937_64 rng(12345);
+  std::normal_distribution<double> nd01;
+  for (auto& v : h) v = nd01(rng);
+  DBuf raw(sizeof(double) * nd, s);
+  Vec v = make_vec(g, 64, 12, 1, 2, 0, s), w = make_vec(g, 64, 12, 1, 2, 0, s),
+      vp = make_vec(g, 64, 12, 1, 2, 0, s), t = make_vec(g, 64, 12, 1, 2, 0, s);
+  if (!raw.p || !v.ok() || !w.ok() || !vp.ok() || !t.ok()) return fail(LQ_ENOMEM, "lanczos buffers");
+  hipMemcpyAsync(raw.p, h.data(), sizeof(double) * nd, hipMemcpyHostToDevice, s);
+  if (launch_pack_field(g, raw.as<double>(), 1, 12, v.f, 64, 2, s)) return fail(LQ_EDEVICE, "pack");
+  std::vector<double> nn;
+  if ((e = col_norms(bl, v, nn))) return e;
+  if ((e = bl.opi(OP_SCALE, &v, nullptr, nullptr, 1.0 / std::sqrt(nn[0])))) return e;
+  if ((e = vec_zero(vp))) return e;
+  std::vector<double> al, be;
+  double beta_prev = 0.0;
+  State st(1, s);
+  for (int j = 0; j < iters; ++j) {
+    if ((e = hw_apply(env, 64, t, v)) || (e = hw_apply(env, 64, w, t))) return e;  // w = H^2 v
+    if ((e = bl.op(OP_DOT, &v, &w))) return e;
+    if (launch_scalar(SC_DOT_TO_AUX, bl.partial, bl.gridx, 1, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if ((e = st.pull())) return e;
+    const double alpha = st.h(0, ST_AUX);
+    al.push_back(alpha);
+    // w = w - alpha v - beta_prev vp
+    if ((e = bl.opi(OP_AXMY, &v, &w, nullptr, alpha))) return e;
+    if ((e = bl.opi(OP_AXMY, &vp, &w, nullptr, beta_prev))) return e;
+    if ((e = col_norms(bl, w, nn))) return e;
+    const double beta = std::sqrt(nn[0]);
+    if (!(beta > 1e-14) || j == iters - 1) break;
+    be.push_back(beta);
+    std::swap(vp, v);
+    if ((e = bl.opi(OP_SCALE, &w, nullptr, nullptr, 1.0 / beta))) return e;
+    std::swap(v, w);
+    beta_prev = beta;
+  }
+  be.resize(al.size() > 0 ? al.size() - 1 : 0);
+  double lo = 0, hi = 0;
+  tridiag_extremes(al, be, lo, hi);
+  *lmin = std::sqrt(std::max(lo, 0.0));
+  *lmax = std::sqrt(std::max(hi, 0.0));
+  return 0;
+}
+
+}  // namespace lq

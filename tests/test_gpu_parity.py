@@ -1,0 +1,303 @@
+"""GPU parity: every HIP operator and solver through the C ABI against the
+FP64 oracle, on seeded synthetic inputs.
+
+Tolerances (relative L2 over the whole output): FP64 storage 1e-13 (stencil)
+and 1e-12 (composite operators), FP32 storage 1e-6, FP16 storage with per-site
+norms 3e-3.  Solutions: FP64 relative true residual <= 1e-10 computed with the
+oracle operator.  Lattices span several 128-site tiles plus a ragged tail.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lattice as lat
+from oracle import wilson as W
+from oracle import staggered as S
+from oracle import overlap as OV
+from oracle import solve as OS
+from paper_2201_09004_amd import lq as L
+
+pytestmark = pytest.mark.gpu
+
+TOL = {64: 1e-13, 32: 1e-6, 16: 3e-3}
+LATS = [(4, 4, 4, 8), (6, 6, 4, 10)]   # Vh = 256 (2 tiles), Vh = 720 (ragged)
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = L.lq_init(0)
+    yield c
+    L.lq_finalize(c)
+
+
+def _wilson_setup(ctx, Lx, seed=1, eps=0.3):
+    U = synth.su3_field(Lx, eps, seed)
+    f = L.lq_gauge_load(ctx, Lx, U)
+    return U, f
+
+
+# ------------------------------------------------------------------ Wilson / TM stencils
+@pytest.mark.parametrize("Lx", LATS)
+@pytest.mark.parametrize("prec", [64, 32, 16])
+def test_wilson_D_and_dagger(ctx, Lx, prec):
+    U, f = _wilson_setup(ctx, Lx, 11)
+    psi = synth.gaussian_spinor(Lx, 2, 12)
+    m = 1.0 / (2 * 0.12) - 4.0
+    act = L.action(L.LQ_WILSON, m=m)
+    try:
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_D, prec, psi)
+        want = np.array([W.wilson(U, p, m) for p in psi])
+        assert rel(out, want) < TOL[prec]
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_DDAG, prec, psi)
+        want = np.array([W.gamma5(W.wilson(U, W.gamma5(p), m)) for p in psi])
+        assert rel(out, want) < TOL[prec]
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_HOP, prec, psi)
+        want = np.array([-0.5 * W.hop(U, p) for p in psi])
+        assert rel(out, want) < TOL[prec]
+    finally:
+        L.lq_field_free(f)
+
+
+@pytest.mark.parametrize("prec", [32, 16])
+def test_wilson_recon12(ctx, prec):
+    Lx = (6, 6, 4, 10)
+    U, f = _wilson_setup(ctx, Lx, 21)
+    psi = synth.gaussian_spinor(Lx, 1, 22)
+    act = L.action(L.LQ_WILSON, m=0.1)
+    try:
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_D, prec | L.LQ_PREC_RECON12, psi)
+        want = W.wilson(U, psi[0], 0.1)[None]
+        assert rel(out, want) < TOL[prec]
+    finally:
+        L.lq_field_free(f)
+
+
+@pytest.mark.parametrize("Lx", LATS)
+@pytest.mark.parametrize("prec", [64, 32])
+def test_tm_clover_operators(ctx, Lx, prec):
+    U, f = _wilson_setup(ctx, Lx, 31, eps=0.4)
+    psi = synth.gaussian_spinor(Lx, 2, 32)
+    m, csw, mu = -0.0695, 1.0509, 0.01
+    act = L.action(L.LQ_TM_CLOVER, m=m, mu=mu, c_sw=csw)
+    tol = 1e-12 if prec == 64 else TOL[prec]
+    try:
+        F = W.field_strength(U)
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_D, prec, psi)
+        want = np.array([W.tm_clover(U, p, m, csw, mu, F=F) for p in psi])
+        assert rel(out, want) < tol
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_DDAG, prec, psi)
+        want = np.array([W.tm_clover_dag(U, p, m, csw, mu, F=F) for p in psi])
+        assert rel(out, want) < tol
+        A = W.site_matrix(U, m, csw, mu, F)
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_SITE, prec, psi)
+        assert rel(out, np.array([W.apply_site(A, p) for p in psi])) < tol
+        Ainv = np.linalg.inv(A)
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_SITE_INV, prec, psi)
+        assert rel(out, np.array([W.apply_site(Ainv, p) for p in psi])) < tol
+        eo = W.EvenOdd(U, m, csw, mu)
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_SCHUR, prec, psi)
+        want = np.array([eo.mhat(p) for p in psi])
+        assert rel(out, want) < tol
+    finally:
+        L.lq_field_free(f)
+
+
+def test_fp16_clover_not_supported(ctx):
+    Lx = (4, 4, 4, 4)
+    U, f = _wilson_setup(ctx, Lx, 41)
+    try:
+        with pytest.raises(L.LqError) as e:
+            L.lq_apply(ctx, L.action(L.LQ_TM_CLOVER, m=0.1, c_sw=1.0), f, L.LQ_OP_D, 16,
+                       synth.gaussian_spinor(Lx, 1, 1))
+        assert e.value.code == L.LQ_ENOTSUP
+    finally:
+        L.lq_field_free(f)
+
+
+def test_empty_and_invalid(ctx):
+    with pytest.raises(L.LqError) as e:
+        L.lq_gauge_load(ctx, (4, 4, 3, 4), np.zeros((4, 3, 4, 4, 4, 3, 3), np.complex128))
+    assert e.value.code == L.LQ_EINVAL
+    with pytest.raises(L.LqError) as e:
+        L.lq_hisq_load(ctx, (2, 4, 4, 4), np.zeros((4, 4, 4, 2, 4, 3, 3), np.complex128),
+                       np.zeros((4, 4, 4, 2, 4, 3, 3), np.complex128))
+    assert e.value.code == L.LQ_EINVAL
+    Lx = (4, 4, 4, 4)
+    U, f = _wilson_setup(ctx, Lx, 42)
+    try:
+        empty = np.zeros((0, 4, 4, 4, 4, 4, 3), np.complex128)
+        out = L.lq_apply(ctx, L.action(L.LQ_WILSON, m=0.1), f, L.LQ_OP_D, 64, empty)
+        assert out.shape[0] == 0
+        with pytest.raises(L.LqError) as e:
+            L.lq_apply(ctx, L.action(L.LQ_WILSON, m=0.1), f, L.LQ_OP_D, 48, synth.gaussian_spinor(Lx, 1, 1))
+        assert e.value.code == L.LQ_EINVAL
+        with pytest.raises(L.LqError) as e:
+            L.lq_apply(ctx, L.action(L.LQ_HISQ, m=0.1), f, L.LQ_OP_D, 64, synth.gaussian_colour(Lx, 1, 1))
+        assert e.value.code == L.LQ_EINVAL
+    finally:
+        L.lq_field_free(f)
+
+
+# ------------------------------------------------------------------ HISQ
+@pytest.mark.parametrize("Lx", [(4, 4, 4, 8), (6, 4, 6, 10)])
+@pytest.mark.parametrize("prec", [64, 32, 16])
+def test_hisq_operators(ctx, Lx, prec):
+    V, Wl = synth.hisq_fields(Lx, 51)
+    f = L.lq_hisq_load(ctx, Lx, V, Wl)
+    chi = synth.gaussian_colour(Lx, 2, 52)
+    m = 0.0102
+    act = L.action(L.LQ_HISQ, m=m)
+    try:
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_D, prec, chi)
+        assert rel(out, np.array([S.hisq(V, Wl, c, m) for c in chi])) < TOL[prec]
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_DDAG, prec, chi)
+        assert rel(out, np.array([S.hisq_dag(V, Wl, c, m) for c in chi])) < TOL[prec]
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_HOP, prec, chi)
+        assert rel(out, np.array([S.hop(V, Wl, c) for c in chi])) < TOL[prec]
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_NORMAL_EVEN, prec, chi)
+        want = np.array([S.even_normal(V, Wl, c * S.even_mask(Lx), m) for c in chi])
+        assert rel(out, want) < 2 * TOL[prec]
+    finally:
+        L.lq_field_free(f)
+
+
+# ------------------------------------------------------------------ overlap
+@pytest.mark.parametrize("prec", [64, 32, 16])
+def test_hw_and_sign(ctx, prec):
+    Lx = (4, 4, 4, 6)
+    rho = 1.5
+    U, f = _wilson_setup(ctx, Lx, 61, eps=0.2)
+    psi = synth.gaussian_spinor(Lx, 2, 62)
+    a, b, N = 0.9 * 0.5 ** 2, 1.1 * 6.5 ** 2, 24
+    c = OV.cheb_coeffs(a, b, N)
+    act = L.action(L.LQ_OVERLAP, m=0.015, rho=rho, cheb_N=N, cheb_a=a, cheb_b=b, cheb_c=c)
+    try:
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_HW, prec, psi)
+        assert rel(out, np.array([OV.hw(U, p, rho) for p in psi])) < TOL[prec]
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_SIGN, prec, psi)
+        want = np.array([OV.sign_hw(U, p, rho, c, a, b) for p in psi])
+        tol = {64: 1e-12, 32: 2e-5, 16: 1e-2}[prec]
+        assert rel(out, want) < tol
+        out = L.lq_apply(ctx, act, f, L.LQ_OP_D, prec, psi)
+        want = np.array([OV.overlap(U, p, rho, 0.015, c, a, b) for p in psi])
+        assert rel(out, want) < tol
+    finally:
+        L.lq_field_free(f)
+
+
+def test_hw_bounds_contain_spectrum(ctx):
+    Lx = (4, 4, 2, 4)
+    U, f = _wilson_setup(ctx, Lx, 71, eps=0.2)
+    try:
+        act = L.action(L.LQ_OVERLAP, m=0.0, rho=1.5, cheb_N=10)
+        lo, hi = L.lq_hw_bounds(ctx, act, f, 300)
+        lo_o, hi_o = OV.hw_extremes(U, 1.5)
+        assert abs(hi - hi_o) < 1e-6 * hi_o
+        assert lo >= lo_o * (1 - 1e-6) and lo < 1.25 * lo_o
+    finally:
+        L.lq_field_free(f)
+
+
+# ------------------------------------------------------------------ solvers
+def _resid(apply, x, b):
+    return max(OS.rel_residual(apply, xi, bi) for xi, bi in zip(x, b))
+
+
+def test_wilson_cgne_fp64(ctx):
+    Lx = (4, 4, 4, 4)
+    U, f = _wilson_setup(ctx, Lx, 81, eps=0.3)
+    m = 1.0 / (2 * 0.12) - 4.0
+    b = synth.gaussian_spinor(Lx, 2, 82)
+    try:
+        x, st = L.lq_solve(ctx, L.action(L.LQ_WILSON, m=m), f, L.params(tol=1e-10, sloppy_bits=64), b)
+        assert st["status"] == 0
+        assert _resid(lambda v: W.wilson(U, v, m), x, b) < 1e-10
+        from oracle import dense
+        D = dense.wilson_tm_clover_dense(U, m)
+        xd = np.linalg.solve(D, b[0].ravel()).reshape(b[0].shape)
+        assert rel(x[0], xd) < 1e-8
+    finally:
+        L.lq_field_free(f)
+
+
+@pytest.mark.parametrize("sloppy", [64, 32])
+def test_tm_clover_eo_bicgstab(ctx, sloppy):
+    Lx = (4, 4, 6, 8)
+    U, f = _wilson_setup(ctx, Lx, 91, eps=0.2)
+    m, csw, mu = -0.0695, 1.0509, 0.01
+    b = synth.point_sources(Lx)[:4]
+    try:
+        act = L.action(L.LQ_TM_CLOVER, m=m, mu=mu, c_sw=csw)
+        x, st = L.lq_solve(ctx, act, f, L.params(tol=1e-10, sloppy_bits=sloppy), b)
+        assert st["status"] == 0, st
+        F = W.field_strength(U)
+        assert _resid(lambda v: W.tm_clover(U, v, m, csw, mu, F=F), x, b) < 1e-10
+        assert st["true_rel_res"] < 1e-10
+    finally:
+        L.lq_field_free(f)
+
+
+@pytest.mark.parametrize("sloppy", [32, 16])
+def test_hisq_multishift(ctx, sloppy):
+    Lx = (4, 4, 4, 8)
+    V, Wl = synth.hisq_fields(Lx, 101)
+    f = L.lq_hisq_load(ctx, Lx, V, Wl)
+    b = synth.staggered_point_sources(Lx, [0, 4], colours=(0, 2))
+    masses = [0.05, 0.02, 0.1]
+    try:
+        act = L.action(L.LQ_HISQ, m=masses[0])
+        y, st = L.lq_solve(ctx, act, f, L.params(tol=1e-10, sloppy_bits=sloppy, masses=masses), b)
+        assert st["status"] == 0, st
+        ev = S.even_mask(Lx)
+        for i, mi in enumerate(masses):
+            r = _resid(lambda v: S.even_normal(V, Wl, v, mi), y[i], b * ev)
+            assert r < 1e-10, (mi, r)
+        x, st = L.lq_solve(ctx, act, f, L.params(tol=1e-10, sloppy_bits=sloppy, masses=masses,
+                                                  reconstruct_full=1), b)
+        for i, mi in enumerate(masses):
+            assert _resid(lambda v: S.hisq(V, Wl, v, mi), x[i], b * ev) < 1e-9
+    finally:
+        L.lq_field_free(f)
+
+
+def test_overlap_cg(ctx):
+    Lx = (4, 4, 4, 4)
+    rho, m = 1.5, 0.05
+    U, f = _wilson_setup(ctx, Lx, 111, eps=0.2)
+    a, b_, N = 0.9 * 0.5 ** 2, 1.1 * 6.5 ** 2, 40
+    lo, hi = OV.hw_extremes(U, rho)
+    assert a < lo * lo and hi * hi < b_
+    c = OV.cheb_coeffs(a, b_, N)
+    b = synth.point_sources(Lx)[:2]
+    try:
+        act = L.action(L.LQ_OVERLAP, m=m, rho=rho, cheb_N=N, cheb_a=a, cheb_b=b_, cheb_c=c)
+        x, st = L.lq_solve(ctx, act, f, L.params(tol=1e-10, sloppy_bits=32, reliable_delta=1e-3), b)
+        assert st["status"] == 0, st
+        assert _resid(lambda v: OV.overlap(U, v, rho, m, c, a, b_), x, b) < 1e-10
+    finally:
+        L.lq_field_free(f)
+
+
+def test_solver_fault_injection(ctx):
+    Lx = (4, 4, 4, 4)
+    U, f = _wilson_setup(ctx, Lx, 121)
+    b = synth.gaussian_spinor(Lx, 1, 122)
+    act = L.action(L.LQ_WILSON, m=0.2)
+    try:
+        with pytest.raises(L.LqError) as e:
+            L.lq_solve(ctx, act, f, L.params(tol=1e-10, fault_inject=1), b)
+        assert e.value.code == L.LQ_ENUMERIC
+        with pytest.raises(L.LqError) as e:
+            L.lq_solve(ctx, act, f, L.params(tol=1e-10, fault_inject=2), b)
+        assert e.value.code == L.LQ_ENOMEM
+        x, st = L.lq_solve(ctx, act, f, L.params(tol=1e-10, fault_inject=3), b)
+        assert st["status"] == L.LQ_ENOCONV
+        assert np.isfinite(x).all()
+    finally:
+        L.lq_field_free(f)
