@@ -179,6 +179,14 @@ lq_status lq_hw_bounds(lq_ctx *ctx, const lq_action *act, const lq_field *g, int
 /* Coefficients c_0..c_N of the Chebyshev interpolant of y^(-1/2) on [a, b] (host, FP64). */
 lq_status lq_cheb_coeffs(double a, double b, int N, double *c);
 
+/* HBM calibration: a plain copy kernel (one 16-byte chunk per lane) moves
+ * `bytes` between two device buffers the library allocates and frees;
+ * after one untimed launch, `reps` launches are timed with HIP events and
+ * *gbs = 2 * bytes / (average launch time) / 1e9 (read + write).  The
+ * measured achievable bandwidth is the denominator reported beside the
+ * 8 TB/s specification.  LQ_ENOMEM if the buffers cannot be allocated. */
+lq_status lq_copy_bandwidth(lq_ctx *ctx, size_t bytes, int reps, double *gbs);
+
 /* Kernel timing with HIP events on the stream each kernel is launched on.
  * enable=1 clears and starts recording; lq_profile_get returns, for kernel
  * family `name` ("wilson", "stag", "blas", ...), the launch count and the

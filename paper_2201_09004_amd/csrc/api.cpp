@@ -283,6 +283,39 @@ lq_status lq_cheb_coeffs(double a, double b, int N, double* c) {
   return LQ_OK;
 }
 
+lq_status lq_copy_bandwidth(lq_ctx* c, size_t bytes, int reps, double* gbs) {
+  if (!c || !gbs || bytes < 16 || reps < 1) return (lq_status)fail(LQ_EINVAL, "need ctx, gbs, bytes >= 16, reps >= 1");
+  hipSetDevice(c->device);
+  bytes = bytes / 16 * 16;
+  void *a = nullptr, *b = nullptr;
+  if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    if (a) hipFree(a);
+    return (lq_status)fail(LQ_ENOMEM, "copy buffers");
+  }
+  hipStream_t s = c->stream;
+  int e = launch_fill_zero(a, bytes, s) || launch_stream_copy(a, b, bytes, s);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  hipEventRecord(e0, s);
+  for (int k = 0; k < reps && !e; ++k) {
+    Prof p(c, "stream_copy", s);
+    e = launch_stream_copy(a, b, bytes, s);
+  }
+  hipEventRecord(e1, s);
+  hipEventSynchronize(e1);
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(a);
+  hipFree(b);
+  if (e) return (lq_status)fail(LQ_EDEVICE, "copy kernel");
+  *gbs = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+  return LQ_OK;
+}
+
 lq_status lq_profile(lq_ctx* c, int enable) {
   if (!c) return (lq_status)fail(LQ_EINVAL, "ctx is NULL");
   prof_flush(c);

@@ -208,18 +208,18 @@ int launch_blas(const BlasArgs& A, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ scalars
-__device__ __forceinline__ cx<double> sum_c(const double* p, int gridx, int k) {
-  cx<double> s = {0, 0};
-  for (int b = 0; b < gridx; ++b) {
-    s.re += p[b * 4 + k];
-    s.im += p[b * 4 + k + 1];
-  }
-  return s;
-}
+// The scalar kernels run one wave (64 lanes) per column; every lane executes
+// the same code and holds the same values.  The partials of a column are
+// summed lane-strided in a fixed order, then by a butterfly whose result is
+// bitwise identical in every lane (fixed order, independent of the batch).
 __device__ __forceinline__ double sum_r(const double* p, int gridx, int k) {
   double s = 0;
-  for (int b = 0; b < gridx; ++b) s += p[b * 4 + k];
+  for (int b = (int)threadIdx.x; b < gridx; b += 64) s += p[b * 4 + k];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   return s;
+}
+__device__ __forceinline__ cx<double> sum_c(const double* p, int gridx, int k) {
+  return {sum_r(p, gridx, k), sum_r(p, gridx, k + 1)};
 }
 __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
   const double d = b.re * b.re + b.im * b.im;
@@ -228,7 +228,7 @@ __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
 __device__ __forceinline__ bool finite_c(cx<double> a) { return isfinite(a.re) && isfinite(a.im); }
 
 __global__ void scalar_kernel(int op, const double* partial, int gridx, int ncol, double* st) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  const int col = blockIdx.x;
   if (col >= ncol) return;
   double* s = st + (int64_t)col * ST_STRIDE;
   const double* p = partial + (int64_t)col * gridx * 4;
@@ -296,7 +296,7 @@ __global__ void scalar_kernel(int op, const double* partial, int gridx, int ncol
 
 int launch_scalar(int op, const double* partial, int gridx, int ncol, double* st, hipStream_t s) {
   if (ncol == 0) return 0;
-  scalar_kernel<<<(ncol + 63) / 64, 64, 0, s>>>(op, partial, gridx, ncol, st);
+  scalar_kernel<<<ncol, 64, 0, s>>>(op, partial, gridx, ncol, st);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(256) ms_p_kernel(MsArgs A) {
 
 // alpha = rr / <p0, A p0>; per shift: zeta_new and alpha_i (shift 0 keeps zeta = 1)
 __global__ void ms_alpha_kernel(MsArgs A, const double* sigma) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.x;
   if (j >= A.nrhs) return;
   double* s = A.st + (int64_t)j * ST_STRIDE;
   const double pap = sum_r(A.partial + (int64_t)j * A.gridx * 4, A.gridx, 0);
@@ -393,7 +393,7 @@ __global__ void ms_alpha_kernel(MsArgs A, const double* sigma) {
 
 // beta = rr_new / rr; beta_i = beta (zeta_new/zeta)^2; rotate zeta; retire shifts
 __global__ void ms_beta_kernel(MsArgs A) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.x;
   if (j >= A.nrhs) return;
   double* s = A.st + (int64_t)j * ST_STRIDE;
   const double rr = sum_r(A.partial + (int64_t)j * A.gridx * 4, A.gridx, 0);
@@ -421,7 +421,7 @@ __global__ void ms_beta_kernel(MsArgs A) {
 }
 
 __global__ void ms_init_kernel(MsArgs A) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.x;
   if (j >= A.nrhs) return;
   double* s = A.st + (int64_t)j * ST_STRIDE;
   const double rr = sum_r(A.partial + (int64_t)j * A.gridx * 4, A.gridx, 0);
@@ -461,15 +461,15 @@ int launch_ms_p(const MsArgs& A, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 int launch_ms_scalar_alpha(const MsArgs& A, const double* sigma, hipStream_t s) {
-  ms_alpha_kernel<<<(A.nrhs + 63) / 64, 64, 0, s>>>(A, sigma);
+  ms_alpha_kernel<<<A.nrhs, 64, 0, s>>>(A, sigma);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 int launch_ms_scalar_beta(const MsArgs& A, hipStream_t s) {
-  ms_beta_kernel<<<(A.nrhs + 63) / 64, 64, 0, s>>>(A);
+  ms_beta_kernel<<<A.nrhs, 64, 0, s>>>(A);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 int launch_ms_init(const MsArgs& A, hipStream_t s) {
-  ms_init_kernel<<<(A.nrhs + 63) / 64, 64, 0, s>>>(A);
+  ms_init_kernel<<<A.nrhs, 64, 0, s>>>(A);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -158,12 +158,13 @@ __global__ void clover_build_kernel(Geom g, const void* links, double csw, doubl
       }
     for (int d = 0; d < 6; ++d) h[7 * d] = h[7 * d] + C{4.0 + m, 0.0};
     // packed Hermitian store: diag pairs then lower triangle in row order
-    double2* hp = H + ((int64_t)(par * 2 + chir) * 18) * g.Vh + cb;
-    for (int kk = 0; kk < 3; ++kk) hp[(int64_t)kk * g.Vh] = make_double2(h[7 * (2 * kk)].re, h[7 * (2 * kk + 1)].re);
+    const int grp = par * 2 + chir;
+    for (int kk = 0; kk < 3; ++kk)
+      H[tix(grp, kk, 18, cb, g.Vh)] = make_double2(h[7 * (2 * kk)].re, h[7 * (2 * kk + 1)].re);
     int kk = 3;
     for (int r = 1; r < 6; ++r)
       for (int cc = 0; cc < r; ++cc) {
-        hp[(int64_t)kk * g.Vh] = make_double2(h[6 * r + cc].re, h[6 * r + cc].im);
+        H[tix(grp, kk, 18, cb, g.Vh)] = make_double2(h[6 * r + cc].re, h[6 * r + cc].im);
         ++kk;
       }
     // A = H +- i mu (g5 = +1 on the upper chirality)
@@ -171,8 +172,7 @@ __global__ void clover_build_kernel(Geom g, const void* links, double csw, doubl
     for (int d = 0; d < 6; ++d) h[7 * d] = h[7 * d] + C{0.0, tw};
     C inv[36];
     inv6(h, inv);
-    double2* ap = Ainv + ((int64_t)(par * 2 + chir) * 36) * g.Vh + cb;
-    for (int e = 0; e < 36; ++e) ap[(int64_t)e * g.Vh] = make_double2(inv[e].re, inv[e].im);
+    for (int e = 0; e < 36; ++e) Ainv[tix(grp, e, 36, cb, g.Vh)] = make_double2(inv[e].re, inv[e].im);
   }
 }
 

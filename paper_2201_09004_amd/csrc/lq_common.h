@@ -1,21 +1,25 @@
 // Device-side building blocks shared by every kernel of liblq:
-// complex arithmetic, lattice geometry, and the even-odd SoA field layouts.
+// complex arithmetic, lattice geometry, and the even-odd field layouts.
 //
 // Field layout in HBM (all precisions): a field is a sequence of "site blocks",
-// one per (column, parity).  A block holds NC complex components per site
-// (NC = 12 for Wilson spinors: spin*3 + colour; NC = 3 for staggered colour
-// vectors) stored component-major, site-minor, so that consecutive lanes of a
-// wave read consecutive sites (coalesced):
-//   FP64: double2        [block][NC][Vh]
-//   FP32: float4 (2 cx)  [block][NC/2][Vh]       (NC = 12)
-//         float2         [block][NC][Vh]         (NC = 3)
-//   FP16: 8 x half (4 cx)[block][NC/4][Vh] + float norm [block][Vh] (NC = 12)
-//         half2          [block][NC][Vh]   + float norm [block][Vh] (NC = 3)
+// one per (column, parity).  A block holds the site data of Vh checkerboard
+// sites as K chunks per site (a chunk is the unit one lane loads: 16 B for
+// FP64 complex, FP32 complex pairs and FP16 complex quads; 8 B / 4 B for the
+// staggered FP32 / FP16 colour components).  Chunks are stored in tiles of
+// LQ_TILE consecutive sites: [block][Vh / LQ_TILE][K][LQ_TILE] (LQ_TILE = 1
+// gives the plain component-plane layout [block][K][Vh]).  A wave of 64
+// consecutive sites then reads whole cache lines for every chunk, and all of
+// a site's data sits within a few kilobytes (few DRAM pages and TLB entries):
+//   FP64: double2        K = NC
+//   FP32: float4 (2 cx)  K = NC/2  (NC = 12)   float2  K = NC (NC = 3)
+//   FP16: 8 x half (4 cx) K = NC/4 (NC = 12)   half2   K = NC (NC = 3)
+//         + float norm [block][Vh]
 // FP16 values are stored divided by the site norm = max |re|,|im| over the
 // site's components (round to nearest even); the norm itself is FP32.
 // block = column * npar + (npar == 2 ? lattice parity : 0).
+// Links and site matrices use the same tiled map with K = elements per site.
+// Vh is a multiple of 8 for even extents, so LQ_TILE = 8 always divides it.
 #pragma once
-
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
@@ -87,7 +91,25 @@ __device__ __forceinline__ int nb_cb(const int c[4], int mu, int k, const Geom& 
   return coords_cb(d, g);
 }
 
+// compiler scheduling fence (no instruction moves across it)
+#ifndef LQ_SCHED_FENCE
+#define LQ_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
+#endif
+
 // ---------------------------------------------------------------- fields
+#ifndef LQ_TILE
+#define LQ_TILE 8
+#endif
+
+// element index of chunk k (of K per site) of site cb in group g of Vh sites
+__host__ __device__ __forceinline__ int64_t tix(int64_t g, int k, int K, int cb, int Vh) {
+#if LQ_TILE > 1
+  return g * (int64_t)K * Vh + (int64_t)(cb / LQ_TILE) * (K * LQ_TILE) + k * LQ_TILE + (cb % LQ_TILE);
+#else
+  return (g * (int64_t)K + k) * Vh + cb;
+#endif
+}
+
 struct FieldRef {
   void* data;
   float* norm;  // FP16 only
@@ -104,53 +126,53 @@ template <int P, int NC> struct IO;
 template <int NC> struct IO<64, NC> {
   using R = double;
   static __device__ __forceinline__ void load(const FieldRef& f, int64_t blk, int cb, cx<R>* v) {
-    const double2* p = (const double2*)f.data + blk * NC * (int64_t)f.Vh + cb;
+    const double2* p = (const double2*)f.data;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      double2 d = p[(int64_t)c * f.Vh];
+      double2 d = p[tix(blk, c, NC, cb, f.Vh)];
       v[c] = {d.x, d.y};
     }
   }
   static __device__ __forceinline__ void store(const FieldRef& f, int64_t blk, int cb, const cx<R>* v) {
-    double2* p = (double2*)f.data + blk * NC * (int64_t)f.Vh + cb;
+    double2* p = (double2*)f.data;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) p[(int64_t)c * f.Vh] = make_double2(v[c].re, v[c].im);
+    for (int c = 0; c < NC; ++c) p[tix(blk, c, NC, cb, f.Vh)] = make_double2(v[c].re, v[c].im);
   }
 };
 
 template <> struct IO<32, 12> {
   using R = float;
   static __device__ __forceinline__ void load(const FieldRef& f, int64_t blk, int cb, cx<R>* v) {
-    const float4* p = (const float4*)f.data + blk * 6 * (int64_t)f.Vh + cb;
+    const float4* p = (const float4*)f.data;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      float4 d = p[(int64_t)k * f.Vh];
+      float4 d = p[tix(blk, k, 6, cb, f.Vh)];
       v[2 * k] = {d.x, d.y};
       v[2 * k + 1] = {d.z, d.w};
     }
   }
   static __device__ __forceinline__ void store(const FieldRef& f, int64_t blk, int cb, const cx<R>* v) {
-    float4* p = (float4*)f.data + blk * 6 * (int64_t)f.Vh + cb;
+    float4* p = (float4*)f.data;
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-      p[(int64_t)k * f.Vh] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+      p[tix(blk, k, 6, cb, f.Vh)] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
   }
 };
 
 template <> struct IO<32, 3> {
   using R = float;
   static __device__ __forceinline__ void load(const FieldRef& f, int64_t blk, int cb, cx<R>* v) {
-    const float2* p = (const float2*)f.data + blk * 3 * (int64_t)f.Vh + cb;
+    const float2* p = (const float2*)f.data;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      float2 d = p[(int64_t)c * f.Vh];
+      float2 d = p[tix(blk, c, 3, cb, f.Vh)];
       v[c] = {d.x, d.y};
     }
   }
   static __device__ __forceinline__ void store(const FieldRef& f, int64_t blk, int cb, const cx<R>* v) {
-    float2* p = (float2*)f.data + blk * 3 * (int64_t)f.Vh + cb;
+    float2* p = (float2*)f.data;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) p[(int64_t)c * f.Vh] = make_float2(v[c].re, v[c].im);
+    for (int c = 0; c < 3; ++c) p[tix(blk, c, 3, cb, f.Vh)] = make_float2(v[c].re, v[c].im);
   }
 };
 
@@ -168,11 +190,11 @@ __device__ __forceinline__ float site_maxabs(const cx<float>* v) {
 template <> struct IO<16, 12> {
   using R = float;
   static __device__ __forceinline__ void load(const FieldRef& f, int64_t blk, int cb, cx<R>* v) {
-    const uint4* p = (const uint4*)f.data + blk * 3 * (int64_t)f.Vh + cb;
+    const uint4* p = (const uint4*)f.data;
     const float n = f.norm[blk * f.Vh + cb];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      uint4 d = p[(int64_t)k * f.Vh];
+      uint4 d = p[tix(blk, k, 3, cb, f.Vh)];
       unsigned w[4] = {d.x, d.y, d.z, d.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j)
@@ -180,7 +202,7 @@ template <> struct IO<16, 12> {
     }
   }
   static __device__ __forceinline__ void store(const FieldRef& f, int64_t blk, int cb, const cx<R>* v) {
-    uint4* p = (uint4*)f.data + blk * 3 * (int64_t)f.Vh + cb;
+    uint4* p = (uint4*)f.data;
     const float n = site_maxabs<12>(v);
     const float s = n > 0.f ? 1.0f / n : 0.f;
     f.norm[blk * f.Vh + cb] = n;
@@ -190,7 +212,7 @@ template <> struct IO<16, 12> {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         w[j] = (unsigned)f2h(s * v[4 * k + j].re) | ((unsigned)f2h(s * v[4 * k + j].im) << 16);
-      p[(int64_t)k * f.Vh] = make_uint4(w[0], w[1], w[2], w[3]);
+      p[tix(blk, k, 3, cb, f.Vh)] = make_uint4(w[0], w[1], w[2], w[3]);
     }
   }
 };
@@ -198,21 +220,22 @@ template <> struct IO<16, 12> {
 template <> struct IO<16, 3> {
   using R = float;
   static __device__ __forceinline__ void load(const FieldRef& f, int64_t blk, int cb, cx<R>* v) {
-    const unsigned* p = (const unsigned*)f.data + blk * 3 * (int64_t)f.Vh + cb;
+    const unsigned* p = (const unsigned*)f.data;
     const float n = f.norm[blk * f.Vh + cb];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      unsigned w = p[(int64_t)c * f.Vh];
+      unsigned w = p[tix(blk, c, 3, cb, f.Vh)];
       v[c] = {n * h2f((unsigned short)(w & 0xffffu)), n * h2f((unsigned short)(w >> 16))};
     }
   }
   static __device__ __forceinline__ void store(const FieldRef& f, int64_t blk, int cb, const cx<R>* v) {
-    unsigned* p = (unsigned*)f.data + blk * 3 * (int64_t)f.Vh + cb;
+    unsigned* p = (unsigned*)f.data;
     const float n = site_maxabs<3>(v);
     const float s = n > 0.f ? 1.0f / n : 0.f;
     f.norm[blk * f.Vh + cb] = n;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) p[(int64_t)c * f.Vh] = (unsigned)f2h(s * v[c].re) | ((unsigned)f2h(s * v[c].im) << 16);
+    for (int c = 0; c < 3; ++c)
+      p[tix(blk, c, 3, cb, f.Vh)] = (unsigned)f2h(s * v[c].re) | ((unsigned)f2h(s * v[c].im) << 16);
   }
 };
 
@@ -220,10 +243,10 @@ template <> struct IO<16, 3> {
 __host__ __device__ inline int site_bytes(int prec, int nc) { return prec == 64 ? nc * 16 : prec == 32 ? nc * 8 : nc * 4; }
 
 // ---------------------------------------------------------------- links
-// Link field layout: T2 elements [parity][mu][NE][Vh] with NE = 9 (full 3x3,
-// row-major) or 6 (first two rows, third reconstructed as conj(row0 x row1)).
-// FP16 links are unscaled for unitary fields; HISQ fields carry a per-field
-// FP32 scale applied by the kernel.
+// Link fields: T2 elements in groups (parity, mu) of NE elements per site
+// (NE = 9: full 3x3 row-major; NE = 6: first two rows, the third rebuilt as
+// conj(row0 x row1)), tiled as the fields above.  FP16 links are unscaled for
+// unitary fields; HISQ fields carry a per-field FP32 scale applied by the kernel.
 template <int P> struct LinkT;
 template <> struct LinkT<64> { using T2 = double2; };
 template <> struct LinkT<32> { using T2 = float2; };
@@ -232,27 +255,26 @@ template <> struct LinkT<16> { using T2 = unsigned; };
 template <int P, int NE>
 __device__ __forceinline__ void load_link(const void* base, int Vh, int par, int mu, int cb,
                                           cx<typename RealOf<P>::T>* U) {
-  using R = typename RealOf<P>::T;
-  const int64_t off = ((int64_t)(par * 4 + mu) * NE) * Vh + cb;
+  const int g = par * 4 + mu;
   if constexpr (P == 64) {
-    const double2* p = (const double2*)base + off;
+    const double2* p = (const double2*)base;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      double2 d = p[(int64_t)e * Vh];
+      double2 d = p[tix(g, e, NE, cb, Vh)];
       U[e] = {d.x, d.y};
     }
   } else if constexpr (P == 32) {
-    const float2* p = (const float2*)base + off;
+    const float2* p = (const float2*)base;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      float2 d = p[(int64_t)e * Vh];
+      float2 d = p[tix(g, e, NE, cb, Vh)];
       U[e] = {d.x, d.y};
     }
   } else {
-    const unsigned* p = (const unsigned*)base + off;
+    const unsigned* p = (const unsigned*)base;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      unsigned w = p[(int64_t)e * Vh];
+      unsigned w = p[tix(g, e, NE, cb, Vh)];
       U[e] = {h2f((unsigned short)(w & 0xffffu)), h2f((unsigned short)(w >> 16))};
     }
   }
@@ -261,7 +283,6 @@ __device__ __forceinline__ void load_link(const void* base, int Vh, int par, int
     U[7] = conj(U[2] * U[3] - U[0] * U[5]);
     U[8] = conj(U[0] * U[4] - U[1] * U[3]);
   }
-  (void)sizeof(R);
 }
 
 // y = U x, y = U^dag x for colour vectors
@@ -295,6 +316,87 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   const int rem_start = per * nx;   // blocks beyond go unmapped
   if (b >= rem_start) return b;
   return (b % nx) * per + b / nx;
+}
+
+// Work decomposition of the stencil kernels.  A workgroup owns one tile of 64
+// consecutive sites (in traversal order) and gw = blockDim.x / 64 column
+// groups, one wave per group, so every column group of a site runs on the same
+// CU and the links and site matrices of the tile are fetched from HBM once.
+// Traversal order within a parity: with slab depth bz > 0 the lattice is cut
+// into slabs of bz z-planes, walked slab by slab with t outside z-in-slab, so
+// the t-neighbours of a site come back Lx/2*Ly*bz sites later (within L2)
+// instead of Lx/2*Ly*Lz; bz = 0 is the lexicographic (x, y, z, t) order.
+// Returns false for lanes without work.
+// Launch shape knobs (tuned): sh = gw | tpb << 8 | xcd << 16 with gw column
+// groups and tpb site tiles per workgroup (one wave each), xcd = 1 to apply
+// xcd_remap to the block index.
+__device__ __forceinline__ bool stencil_site(const Geom& g, int par_out, int bz, int ngrp, int sh, int& par, int& cb,
+                                             int& grp, int c[4]) {
+  const int nsite = par_out == 2 ? 2 * g.Vh : g.Vh;
+  const int ntile = (nsite + 63) >> 6;
+  const int gw = sh & 0xff, tpb = (sh >> 8) & 0xff;
+  const int nchunk = (ngrp + gw - 1) / gw;
+  const int lb = ((sh >> 16) & 1) ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int bt = lb / nchunk;
+  // the wave index is uniform across the wave: keep it (and the column group
+  // and field base addresses derived from it) in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tile = bt * tpb + w / gw;
+  grp = (lb - bt * nchunk) * gw + (w % gw);
+  const int j = tile * 64 + (threadIdx.x & 63);
+  // Waves past the last column group (grp >= ngrp, when gw does not divide
+  // ngrp) are not turned away here: the kernels give them no columns
+  // (ncol - grp*NR <= 0), so they only read valid addresses and store
+  // nothing.  An explicit grp check lets the compiler prove every column
+  // guard true and merge the whole stencil into one block, which doubles
+  // register use and spills.
+  (void)ngrp;
+  if (tile >= ntile || j >= nsite) return false;
+  par = par_out == 2 ? (j >= g.Vh ? 1 : 0) : par_out;
+  const int jj = par_out == 2 ? j - par * g.Vh : j;
+  const int xh = jj % g.Lxh;
+  int r = jj / g.Lxh;
+  c[1] = r % g.L[1];
+  r /= g.L[1];
+  if (bz > 0) {
+    const int zi = r % bz;
+    r /= bz;
+    c[3] = r % g.L[3];
+    c[2] = (r / g.L[3]) * bz + zi;
+  } else {
+    c[2] = r % g.L[2];
+    c[3] = r / g.L[2];
+  }
+  c[0] = 2 * xh + ((c[1] + c[2] + c[3] + par) & 1);
+  cb = xh + g.Lxh * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+  return true;
+}
+
+// launch shape matching stencil_site: 64 sites x gw groups per workgroup, at
+// most 8 waves (the kernels declare 512-thread launch bounds so that the
+// register-blocked variants keep up to 256 VGPRs without spilling)
+constexpr int kStencilMaxThreads = 256;
+struct StencilGrid {
+  int blocks, threads, sh;
+};
+// tpb_req: requested site tiles per workgroup (0: enough for >= 4 waves);
+// xcd: apply the XCD-aware block order
+inline StencilGrid stencil_grid(int nsite, int ngrp, int tpb_req, int xcd) {
+  const int maxw = kStencilMaxThreads / 64;
+  // column groups per workgroup: the largest divisor of ngrp that fits, so no
+  // wave of a workgroup is left without columns
+  int gw = 1;
+  for (int d = maxw; d > 1; --d)
+    if (ngrp % d == 0) {
+      gw = d;
+      break;
+    }
+  int tpb = tpb_req > 0 ? tpb_req : (gw >= 4 ? 1 : 4 / gw);
+  if (tpb * gw > maxw) tpb = maxw / gw;
+  if (tpb < 1) tpb = 1;
+  const int nchunk = (ngrp + gw - 1) / gw;
+  const int ntile = (nsite + 63) / 64;
+  return {((ntile + tpb - 1) / tpb) * nchunk, 64 * gw * tpb, gw | (tpb << 8) | ((xcd ? 1 : 0) << 16)};
 }
 
 }  // namespace lq

@@ -28,6 +28,14 @@ struct ProfRec {
   hipEvent_t a, b;
 };
 
+// tuned launch shape of a stencil kernel
+struct Shape {
+  int nr;    // columns per thread
+  int slab;  // traversal slab depth (0: lexicographic)
+  int tpb;   // site tiles per workgroup (0: automatic)
+  int xcd;   // XCD-aware block order
+};
+
 }  // namespace lq
 
 struct lq_ctx {
@@ -40,6 +48,9 @@ struct lq_ctx {
   double* partial = nullptr;  // reduction partials
   size_t partial_bytes = 0;
   std::mutex mtx;
+  // autotuned launch shapes per kernel key
+  std::map<std::string, lq::Shape> tune;
+  bool tune_loaded = false;
 };
 
 namespace lq {

@@ -17,7 +17,11 @@ struct WilsonArgs {
   Geom g;
   int prec, recon, dag, epi;
   int par_out;  // 0, 1, or 2 = both parities
-  int ncol, block;
+  int ncol;
+  int slab;     // traversal slab depth in z (0: lexicographic), see stencil_site
+  int tpb, xcd; // site tiles per workgroup (0: automatic), XCD-aware block order
+  int sh;       // packed launch shape, set by the launcher
+  int nr;       // columns per thread (register blocking): 1, 2, 3, 4 or 6
   const void* links;
   FieldRef in, out, x, v, b1, b2;
   const void* clov;      // packed Hermitian H = (4+m) + C per chirality
@@ -26,6 +30,8 @@ struct WilsonArgs {
   double a, k_hop, mu_tw, s1, ck, s2;
 };
 int launch_wilson(const WilsonArgs& A, hipStream_t s);
+template <int P>
+int launch_wilson_prec(const WilsonArgs& A, int nr, int bs, hipStream_t s);
 
 // site term of the twisted-clover operator: out = A x or A^{-1} x per site
 int launch_site(const Geom& g, int prec, const void* clov, const void* clov_inv, double mu_tw, bool inverse,
@@ -36,7 +42,11 @@ enum { SEPI_HOP = 0, SEPI_XPAY };
 
 struct StagArgs {
   Geom g;
-  int prec, epi, par_out, ncol, block;
+  int prec, epi, par_out, ncol;
+  int slab;      // traversal slab depth in z (0: lexicographic), see stencil_site
+  int tpb, xcd;  // site tiles per workgroup (0: automatic), XCD-aware block order
+  int sh;        // packed launch shape, set by the launcher
+  int nr;  // columns per thread: 1, 2, 3, 4, 6 or 8
   const void* fat;
   const void* lng;
   float sfat, slong;
@@ -124,5 +134,6 @@ int launch_ms_init(const MsArgs& A, hipStream_t s);
 
 // profiling-free utilities
 int launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+int launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 }  // namespace lq

@@ -214,13 +214,158 @@ static double wilson_bytes(int prec, int recon, int n_fields, int ncol, int clov
   return link + clov + (double)ncol * n_fields * spin;
 }
 
+// ------------------------------------------------------------------ autotuner
+// Launch shapes (columns per thread NR, traversal slab depth) are chosen per
+// kernel key by timing every candidate on the real operands into a scratch
+// output (all candidates compute each column with identical arithmetic).
+// LQ_TUNE=0 disables tuning (NR=1, lexicographic order); LQ_TUNE_CACHE=<file>
+// persists choices.
+static bool tune_enabled() {
+  const char* v = getenv("LQ_TUNE");
+  return !(v && v[0] == '0');
+}
+
+static void tune_load(lq_ctx* c) {
+  if (c->tune_loaded) return;
+  c->tune_loaded = true;
+  const char* path = getenv("LQ_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char key[256];
+  Shape sh{};
+  while (fscanf(f, "%255s %d %d %d %d", key, &sh.nr, &sh.slab, &sh.tpb, &sh.xcd) == 5) c->tune[key] = sh;
+  fclose(f);
+}
+
+static void tune_save(lq_ctx* c) {
+  const char* path = getenv("LQ_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  for (auto& kv : c->tune)
+    fprintf(f, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.nr, kv.second.slab, kv.second.tpb, kv.second.xcd);
+  fclose(f);
+}
+
+// slab depths worth trying for a lattice: 0 (lexicographic) and divisors of Lz
+static std::vector<int> slab_candidates(const Geom& g) {
+  std::vector<int> v{0};
+  for (int bz : {1, 2, 4, 8})
+    if (g.L[2] % bz == 0 && bz < g.L[2]) v.push_back(bz);
+  return v;
+}
+
+template <typename Args>
+static void apply_shape(Args& A, const Shape& sh) {
+  A.nr = sh.nr;
+  A.slab = sh.slab;
+  A.tpb = sh.tpb;
+  A.xcd = sh.xcd;
+}
+
+template <typename Args, typename LaunchFn>
+static int tuned(lq_ctx* c, const std::string& key, Args& A, size_t out_bytes, int prec,
+                 const std::vector<int>& nrs, hipStream_t s, LaunchFn launch) {
+  const std::vector<int> slabs = slab_candidates(A.g);
+  Shape choice{1, 0, 0, 1};
+  if (const char* f = getenv("LQ_TUNE_FORCE")) {
+    // testing hook: force "nr,slab[,tpb,xcd]" wherever the values are candidates
+    int nr = 1, bz = 0, tpb = 0, xcd = 1;
+    if (sscanf(f, "%d,%d,%d,%d", &nr, &bz, &tpb, &xcd) >= 2) {
+      Shape sh{std::find(nrs.begin(), nrs.end(), nr) != nrs.end() ? nr : 1,
+               std::find(slabs.begin(), slabs.end(), bz) != slabs.end() ? bz : 0,
+               (tpb == 1 || tpb == 2 || tpb == 4 || tpb == 8) ? tpb : 0, xcd ? 1 : 0};
+      apply_shape(A, sh);
+      return launch(A, s);
+    }
+  }
+  bool need = false;
+  {
+    std::lock_guard<std::mutex> lk(c->mtx);
+    tune_load(c);
+    auto it = c->tune.find(key);
+    if (it != c->tune.end()) choice = it->second;
+    else if (!tune_enabled()) c->tune[key] = choice;
+    else need = true;
+  }
+  if (need) {
+    // scratch output: main part rounded to 256 bytes, FP16 norms after it
+    const size_t main_bytes = (out_bytes + 255) / 256 * 256;
+    const size_t norm_bytes = prec == 16 ? out_bytes / 3 + 256 : 0;  // >= sites * 4 (FP16 site_bytes >= 12)
+    DBuf scratch(main_bytes + norm_bytes, s);
+    Args B = A;
+    B.out.data = scratch.p;
+    if (prec == 16) B.out.norm = (float*)((char*)scratch.p + main_bytes);
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best = 1e30f;
+    auto trial = [&](const Shape& sh) {
+      apply_shape(B, sh);
+      if (!scratch.p || launch(B, s)) {
+        (void)hipGetLastError();
+        return;
+      }
+      hipEventRecord(e0, s);
+      for (int k = 0; k < 3; ++k) launch(B, s);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        choice = sh;
+      }
+    };
+    // stage 1: columns per thread x slab depth; stage 2: tiles per workgroup x block order
+    for (int nr : nrs)
+      for (int bz : slabs) trial(Shape{nr, bz, 0, 1});
+    const Shape s1 = choice;
+    for (int tpb : {0, 1, 2, 4, 8})
+      for (int xcd : {1, 0})
+        if (!(tpb == 0 && xcd == 1)) trial(Shape{s1.nr, s1.slab, tpb, xcd});
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(c->mtx);
+    c->tune[key] = choice;
+    tune_save(c);
+  }
+  apply_shape(A, choice);
+  return launch(A, s);
+}
+
+// bytes of the value part of an output with ncol columns x npar parities
+// (FP16: site_bytes >= 12, so a third of it covers the 4-byte site norms)
+static size_t tune_out_bytes(int prec, int nc, int ncol, int npar, int Vh) {
+  return (size_t)ncol * npar * Vh * (size_t)site_bytes(prec, nc);
+}
+
+static std::vector<int> nr_candidates(int prec, int ncol, bool blocked) {
+  std::vector<int> v{1};
+  if (!blocked) return v;
+  for (int nr : {2, 3, 4, 6})
+    if (nr <= ncol && !(prec == 64 && nr > 4)) v.push_back(nr);
+  return v;
+}
+
 static int run_wilson(OpEnv& e, WilsonArgs& A, int n_fields, int clov_mats, int flops_extra) {
   A.g = e.f->g;
   A.recon = (e.recon && A.prec != 64) ? 1 : 0;
   if (!A.links) return fail(LQ_EDEVICE, "links not packed");
   const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
-  Prof p(e.ctx, "wilson", e.s);
-  int r = launch_wilson(A, e.s);
+  static const char* epi_names[] = {"hop", "xpay", "xpay_g5", "clovinv", "xmy", "site", "cheb"};
+  char name[48];
+  snprintf(name, sizeof(name), "wilson%d_%s", A.prec, epi_names[A.epi]);
+  char key[160];
+  snprintf(key, sizeof(key), "%s_r%d_d%d_n%d_v%d_p%d", name, A.recon, A.dag, A.ncol, A.g.Vh, A.par_out);
+  const bool blocked = !A.dag && (A.epi == EPI_CLOVINV || A.epi == EPI_XMY_CLOVINV || A.epi == EPI_XPAY ||
+                                  A.epi == EPI_XPAY_G5 || A.epi == EPI_CHEB);
+  const int out_npar = A.out.npar;
+  Prof p(e.ctx, name, e.s);
+  int r = tuned(e.ctx, key, A, tune_out_bytes(A.prec, 12, A.ncol, out_npar, A.g.Vh), A.prec,
+                nr_candidates(A.prec, A.ncol, blocked), e.s,
+                [](const WilsonArgs& B, hipStream_t st) { return launch_wilson(B, st); });
   if (r) return fail(r == -1 ? LQ_ENOTSUP : LQ_EDEVICE, "wilson stencil launch");
   e.n_apply += A.par_out == 2 ? 2 : 1;
   e.flops += (double)nsite * A.ncol * (1320.0 + flops_extra);
@@ -497,8 +642,17 @@ static int run_stag(OpEnv& e, StagArgs& A, int n_fields) {
   A.sfat = e.f->sfat[pi];
   A.slong = e.f->slng[pi];
   const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
-  Prof p(e.ctx, "stag", e.s);
-  if (launch_stag(A, e.s)) return fail(LQ_EDEVICE, "staggered stencil launch");
+  char name[48];
+  snprintf(name, sizeof(name), "stag%d_%s", A.prec, A.epi == SEPI_HOP ? "hop" : "xpay");
+  char key[160];
+  snprintf(key, sizeof(key), "%s_n%d_v%d_p%d", name, A.ncol, A.g.Vh, A.par_out);
+  std::vector<int> nrs{1};
+  for (int nr : {2, 3, 4, 6, 8})
+    if (nr <= A.ncol && !(A.prec == 64 && nr > 4)) nrs.push_back(nr);
+  Prof p(e.ctx, name, e.s);
+  if (tuned(e.ctx, key, A, tune_out_bytes(A.prec, 3, A.ncol, A.out.npar, A.g.Vh), A.prec, nrs, e.s,
+            [](const StagArgs& B, hipStream_t st) { return launch_stag(B, st); }))
+    return fail(LQ_EDEVICE, "staggered stencil launch");
   e.n_apply += A.par_out == 2 ? 2 : 1;
   const double rb = A.prec == 64 ? 8 : A.prec == 32 ? 4 : 2;
   e.flops += (double)nsite * A.ncol * 1146.0;

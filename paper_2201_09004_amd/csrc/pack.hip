@@ -49,12 +49,11 @@ __global__ void pack_links_kernel(Geom g, const double2* aos, void* out, int ne,
     if (mu == 3 && g.ap && c[3] + hisq_hop >= g.L[3]) f = -f;
   }
   const double2* src = aos + (s * 4 + mu) * 9;
-  const int64_t base = ((int64_t)(par * 4 + mu) * ne) * g.Vh + cb;
   for (int e = 0; e < ne; ++e) {
     double2 d = src[e];
     d.x *= f;
     d.y *= f;
-    const int64_t o = base + (int64_t)e * g.Vh;
+    const int64_t o = tix(par * 4 + mu, e, ne, cb, g.Vh);
     if constexpr (P == 64) ((double2*)out)[o] = d;
     else if constexpr (P == 32) ((float2*)out)[o] = make_float2((float)d.x, (float)d.y);
     else ((unsigned*)out)[o] = (unsigned)f2h((float)d.x) | ((unsigned)f2h((float)d.y) << 16);
@@ -278,6 +277,24 @@ int launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   const int64_t n = n16 > ntail ? n16 : ntail;
   const int bs = 256;
   fill_zero_kernel<<<(int)((n + bs - 1) / bs), bs, 0, s>>>((uint4*)p, n16, (unsigned char*)p + n16 * 16, ntail);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace lq
+
+namespace lq {
+
+// Calibration copy: one 16-byte chunk per lane, read once and written once.
+__global__ void __launch_bounds__(256) stream_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                          int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+int launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 16);
+  if (n == 0) return 0;
+  stream_copy_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>((const uint4*)src, (uint4*)dst, n);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

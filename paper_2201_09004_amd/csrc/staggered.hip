@@ -11,103 +11,119 @@
 //   SEPI_HOP   out = k hop
 //   SEPI_XPAY  out = a_col x + k hop      (D = m + hop; M_e = m^2 - D_eo D_oe)
 // FP16 links are stored divided by one FP32 scale per field (fat, long).
+// One thread owns one site and NR consecutive columns: the 16 links of a site
+// are loaded once for all NR columns (bitwise-identical per-column results
+// for every NR).
 #include "lq_common.h"
 #include "lq_kernels.h"
 
 namespace lq {
 
-template <int P, int MU, typename R>
-__device__ __forceinline__ void stag_dir(const StagArgs& A, const int c[4], int par, int cb, int col,
-                                         cx<R>* af, cx<R>* al) {
+template <int P, int MU, int K, bool LONG, int NR, typename R>
+__device__ __forceinline__ void stag_hop1(const StagArgs& A, const int c[4], int par, int cb, int col0, int nv,
+                                          cx<R> (*acc)[3]) {
   const Geom& g = A.g;
   const int pin = par ^ 1;
-  const int64_t bi = blk_index(A.in, col, pin);
-  cx<R> U[9], x[3], y[3];
-  {
-    const int nb = nb_cb(c, MU, 1, g);
-    IO<P, 3>::load(A.in, bi, nb, x);
-    load_link<P, 9>(A.fat, g.Vh, par, MU, cb, U);
-    su3_mv(U, x, y);
+  cx<R> U[9];
+  const void* links = LONG ? A.lng : A.fat;
+  const int nb = nb_cb(c, MU, K, g);
+  if constexpr (K > 0) load_link<P, 9>(links, g.Vh, par, MU, cb, U);
+  else load_link<P, 9>(links, g.Vh, pin, MU, nb, U);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) af[a] = af[a] + y[a];
-  }
-  {
-    const int nb = nb_cb(c, MU, -1, g);
-    IO<P, 3>::load(A.in, bi, nb, x);
-    load_link<P, 9>(A.fat, g.Vh, pin, MU, nb, U);
-    su3_mv_dag(U, x, y);
+  for (int r = 0; r < NR; ++r) {
+    if (r < nv) {
+      cx<R> x[3], y[3];
+      IO<P, 3>::load(A.in, blk_index(A.in, col0 + r, pin), nb, x);
+      if constexpr (K > 0) {
+        su3_mv(U, x, y);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) af[a] = af[a] - y[a];
-  }
-  {
-    const int nb = nb_cb(c, MU, 3, g);
-    IO<P, 3>::load(A.in, bi, nb, x);
-    load_link<P, 9>(A.lng, g.Vh, par, MU, cb, U);
-    su3_mv(U, x, y);
+        for (int a = 0; a < 3; ++a) acc[r][a] = acc[r][a] + y[a];
+      } else {
+        su3_mv_dag(U, x, y);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) al[a] = al[a] + y[a];
+        for (int a = 0; a < 3; ++a) acc[r][a] = acc[r][a] - y[a];
+      }
+    }
   }
-  {
-    const int nb = nb_cb(c, MU, -3, g);
-    IO<P, 3>::load(A.in, bi, nb, x);
-    load_link<P, 9>(A.lng, g.Vh, pin, MU, nb, U);
-    su3_mv_dag(U, x, y);
+}
+
+template <int P, int MU, int NR, typename R>
+__device__ __forceinline__ void stag_dir(const StagArgs& A, const int c[4], int par, int cb, int col0, int nv,
+                                         cx<R> (*af)[3], cx<R> (*al)[3]) {
+  stag_hop1<P, MU, 1, false, NR>(A, c, par, cb, col0, nv, af);
+  stag_hop1<P, MU, -1, false, NR>(A, c, par, cb, col0, nv, af);
+  stag_hop1<P, MU, 3, true, NR>(A, c, par, cb, col0, nv, al);
+  stag_hop1<P, MU, -3, true, NR>(A, c, par, cb, col0, nv, al);
+}
+
+template <int P, int EPI, int NR>
+__global__ void __launch_bounds__(kStencilMaxThreads) stag_kernel(StagArgs A) {
+  using R = typename RealOf<P>::T;
+  const int ngrp = (A.ncol + NR - 1) / NR;
+  int par, cb, grp, c[4];
+  if (!stencil_site(A.g, A.par_out, A.slab, ngrp, A.sh, par, cb, grp, c)) return;
+  const int col0 = grp * NR;
+  const int nv = min(NR, A.ncol - col0);
+  cx<R> af[NR][3], al[NR][3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) al[a] = al[a] - y[a];
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) af[r][a] = al[r][a] = {0, 0};
+  stag_dir<P, 0, NR>(A, c, par, cb, col0, nv, af, al);
+  stag_dir<P, 1, NR>(A, c, par, cb, col0, nv, af, al);
+  stag_dir<P, 2, NR>(A, c, par, cb, col0, nv, af, al);
+  stag_dir<P, 3, NR>(A, c, par, cb, col0, nv, af, al);
+  const R kf = (R)(A.k_hop * A.sfat), kl = (R)(A.k_hop * A.slong);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nv) continue;
+    const int col = col0 + r;
+    cx<R> out[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a] = kf * af[r][a] + kl * al[r][a];
+    if constexpr (EPI == SEPI_XPAY) {
+      cx<R> x[3];
+      IO<P, 3>::load(A.x, blk_index(A.x, col, par), cb, x);
+      const R a = A.acol ? (R)A.acol[col] : (R)A.a;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) out[i] = a * x[i] + out[i];
+    }
+    IO<P, 3>::store(A.out, blk_index(A.out, col, par), cb, out);
   }
+}
+
+template <int P, int EPI, int NR>
+static void stag_one(const StagArgs& A, int bs, hipStream_t s) {
+  (void)bs;
+  const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
+  const StencilGrid G = stencil_grid(nsite, (A.ncol + NR - 1) / NR, A.tpb, A.xcd);
+  StagArgs B = A;
+  B.sh = G.sh;
+  stag_kernel<P, EPI, NR><<<dim3(G.blocks), dim3(G.threads), 0, s>>>(B);
 }
 
 template <int P, int EPI>
-__global__ void __launch_bounds__(256) stag_kernel(StagArgs A) {
-  using R = typename RealOf<P>::T;
-  const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
-  const int ntile = (nsite + blockDim.x - 1) / blockDim.x;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = lb / A.ncol;
-  const int col = lb % A.ncol;
-  const int j = tile * blockDim.x + threadIdx.x;
-  if (tile >= ntile || j >= nsite) return;
-  int par, cb;
-  if (A.par_out == 2) {
-    par = j >= A.g.Vh;
-    cb = j - par * A.g.Vh;
-  } else {
-    par = A.par_out;
-    cb = j;
+static int stag_nr(const StagArgs& A, int nr, int bs, hipStream_t s) {
+  switch (nr) {
+    case 1: stag_one<P, EPI, 1>(A, bs, s); return 0;
+    case 2: stag_one<P, EPI, 2>(A, bs, s); return 0;
+    case 3: stag_one<P, EPI, 3>(A, bs, s); return 0;
+    case 4: stag_one<P, EPI, 4>(A, bs, s); return 0;
+    case 6: stag_one<P, EPI, 6>(A, bs, s); return 0;
+    case 8: stag_one<P, EPI, 8>(A, bs, s); return 0;
+    default: return -1;
   }
-  int c[4];
-  cb_coords(cb, par, A.g, c);
-  cx<R> af[3] = {{0, 0}, {0, 0}, {0, 0}}, al[3] = {{0, 0}, {0, 0}, {0, 0}};
-  stag_dir<P, 0>(A, c, par, cb, col, af, al);
-  stag_dir<P, 1>(A, c, par, cb, col, af, al);
-  stag_dir<P, 2>(A, c, par, cb, col, af, al);
-  stag_dir<P, 3>(A, c, par, cb, col, af, al);
-  const R kf = (R)(A.k_hop * A.sfat), kl = (R)(A.k_hop * A.slong);
-  cx<R> out[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) out[a] = kf * af[a] + kl * al[a];
-  if constexpr (EPI == SEPI_XPAY) {
-    cx<R> x[3];
-    IO<P, 3>::load(A.x, blk_index(A.x, col, par), cb, x);
-    const R a = A.acol ? (R)A.acol[col] : (R)A.a;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) out[i] = a * x[i] + out[i];
-  }
-  IO<P, 3>::store(A.out, blk_index(A.out, col, par), cb, out);
 }
 
 int launch_stag(const StagArgs& A, hipStream_t s) {
-  const int bs = A.block > 0 ? A.block : 128;
-  const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
-  const int ntile = (nsite + bs - 1) / bs;
-  dim3 grid(ntile * A.ncol), block(bs);
-#define LQ_SL(PP)                                                                    \
-  if (A.epi == SEPI_HOP) stag_kernel<PP, SEPI_HOP><<<grid, block, 0, s>>>(A);          \
-  else stag_kernel<PP, SEPI_XPAY><<<grid, block, 0, s>>>(A);
-  if (A.prec == 64) { LQ_SL(64) }
-  else if (A.prec == 32) { LQ_SL(32) }
-  else { LQ_SL(16) }
-#undef LQ_SL
+  const int nr = A.nr > 0 ? A.nr : 1;
+  if (A.slab < 0 || (A.slab > 0 && A.g.L[2] % A.slab != 0)) return -1;
+  const int bs = 0;
+  int r;
+  if (A.prec == 64) r = A.epi == SEPI_HOP ? stag_nr<64, SEPI_HOP>(A, nr, bs, s) : stag_nr<64, SEPI_XPAY>(A, nr, bs, s);
+  else if (A.prec == 32) r = A.epi == SEPI_HOP ? stag_nr<32, SEPI_HOP>(A, nr, bs, s) : stag_nr<32, SEPI_XPAY>(A, nr, bs, s);
+  else r = A.epi == SEPI_HOP ? stag_nr<16, SEPI_HOP>(A, nr, bs, s) : stag_nr<16, SEPI_XPAY>(A, nr, bs, s);
+  if (r) return r;
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblq.so")
+# LQ_LIB selects another build of the same library (e.g. a layout variant)
+LIB_PATH = os.environ.get("LQ_LIB", os.path.join(HERE, "liblq.so"))
 
 LQ_OK, LQ_EINVAL, LQ_ENOMEM, LQ_EDEVICE, LQ_ENOCONV, LQ_EBREAKDOWN, LQ_ENUMERIC, LQ_EBUSY, LQ_ENOTSUP = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
@@ -27,7 +28,7 @@ LQ_PREC_RECON12 = 0x100
 EXPORTS = [
     "lq_init", "lq_finalize", "lq_last_error", "lq_version", "lq_gauge_load", "lq_gauge_load_dev",
     "lq_hisq_load", "lq_hisq_load_dev", "lq_field_free", "lq_apply", "lq_apply_dev", "lq_solve",
-    "lq_solve_dev", "lq_hw_bounds", "lq_cheb_coeffs", "lq_profile", "lq_profile_get",
+    "lq_solve_dev", "lq_hw_bounds", "lq_cheb_coeffs", "lq_copy_bandwidth", "lq_profile", "lq_profile_get",
     "lq_server_create", "lq_server_destroy", "lq_submit", "lq_poll", "lq_wait", "lq_server_stats",
 ]
 
@@ -100,6 +101,7 @@ def load():
                           P], C.c_int),
         "lq_hw_bounds": ([P, C.POINTER(lq_action), P, C.c_int, D, D], C.c_int),
         "lq_cheb_coeffs": ([C.c_double, C.c_double, C.c_int, D], C.c_int),
+        "lq_copy_bandwidth": ([P, C.c_size_t, C.c_int, D], C.c_int),
         "lq_profile": ([P, C.c_int], C.c_int),
         "lq_profile_get": ([P, C.c_char_p, C.POINTER(C.c_int64), D], C.c_int),
         "lq_server_create": ([P, C.c_size_t, C.c_int, C.POINTER(P)], C.c_int),
@@ -271,6 +273,12 @@ def lq_cheb_coeffs(a, b, N):
     c = np.zeros(N + 1)
     _check(load().lq_cheb_coeffs(a, b, N, c.ctypes.data_as(C.POINTER(C.c_double))))
     return c
+
+
+def lq_copy_bandwidth(ctx, nbytes, reps=20):
+    g = C.c_double()
+    _check(load().lq_copy_bandwidth(ctx, C.c_size_t(int(nbytes)), reps, C.byref(g)))
+    return g.value
 
 
 def lq_profile(ctx, enable=True):

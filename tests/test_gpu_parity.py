@@ -301,3 +301,49 @@ def test_solver_fault_injection(ctx):
         assert np.isfinite(x).all()
     finally:
         L.lq_field_free(f)
+
+
+# ------------------------------------------------------------------ autotuner variants
+FORCES = ["1,0", "2,2", "3,1", "4,0", "6,2", "8,1"]   # "columns per thread, slab depth"
+
+
+@pytest.mark.parametrize("prec", [64, 32, 16])
+def test_column_blocking_bitwise_identical(ctx, prec, monkeypatch):
+    """Every (columns per thread, block size) launch shape the tuner can pick
+    gives bitwise-identical results (7 columns: ragged column groups)."""
+    Lx = (6, 6, 4, 10)
+    U, f = _wilson_setup(ctx, Lx, 131)
+    psi = synth.gaussian_spinor(Lx, 7, 132)
+    if prec == 16:
+        act, op = L.action(L.LQ_OVERLAP, m=0.0, rho=1.5, cheb_N=2, cheb_a=0.3, cheb_b=48.0), L.LQ_OP_HW
+    else:
+        act, op = L.action(L.LQ_TM_CLOVER, m=-0.0695, mu=0.01, c_sw=1.0509), L.LQ_OP_SCHUR
+    try:
+        outs = []
+        for force in FORCES:
+            monkeypatch.setenv("LQ_TUNE_FORCE", force)
+            outs.append(L.lq_apply(ctx, act, f, op, prec, psi))
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0])
+    finally:
+        L.lq_field_free(f)
+
+
+@pytest.mark.parametrize("prec", [64, 16])
+def test_hisq_column_blocking_bitwise_identical(ctx, prec, monkeypatch):
+    Lx = (6, 4, 6, 10)
+    V, Wl = synth.hisq_fields(Lx, 141)
+    f = L.lq_hisq_load(ctx, Lx, V, Wl)
+    chi = synth.gaussian_colour(Lx, 7, 142)
+    act = L.action(L.LQ_HISQ, m=0.02)
+    try:
+        outs = []
+        for force in FORCES:
+            monkeypatch.setenv("LQ_TUNE_FORCE", force)
+            outs.append(L.lq_apply(ctx, act, f, L.LQ_OP_NORMAL_EVEN, prec, chi))
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0])
+        want = np.array([S.even_normal(V, Wl, c * S.even_mask(Lx), 0.02) for c in chi])
+        assert rel(outs[0], want) < 2 * TOL[prec]
+    finally:
+        L.lq_field_free(f)
