@@ -42,7 +42,8 @@ def stencil_bytes_per_site(epi: str, n_rhs: int) -> float:
     links = 8 * 18 * 4
     clov = 144 * 4
     spin = 24 * 4
-    nfield = {"clovinv": 2, "xmy": 3}[epi]
+    # xmyd also reads rhat for the fused <rhat, v>; xmyt reuses x for <t, s>
+    nfield = {"clovinv": 2, "xmy": 3, "xmyd": 4, "xmyt": 3}[epi]
     return links + clov + n_rhs * nfield * spin
 
 
@@ -136,8 +137,8 @@ def main():
 
     # roofline of the dominant stencil kernel from the HIP events of the timed region
     kernels = {}
-    for name in ("wilson32_clovinv", "wilson32_xmy", "wilson64_clovinv", "wilson64_xmy", "wilson64_site",
-                 "wilson64_xpay", "blas", "site"):
+    for name in ("wilson32_clovinv", "wilson32_xmy", "wilson32_xmyd", "wilson32_xmyt", "wilson64_clovinv",
+                 "wilson64_xmy", "wilson64_site", "wilson64_xpay", "blas", "site"):
         n, avg = L.lq_profile_get(ctx, name)
         if n:
             kernels[name] = {"count": n, "avg_ms": avg, "total_ms": n * avg}

@@ -194,11 +194,34 @@ lq_status lq_copy_bandwidth(lq_ctx *ctx, size_t bytes, int reps, double *gbs);
 lq_status lq_profile(lq_ctx *ctx, int enable);
 lq_status lq_profile_get(lq_ctx *ctx, const char *name, int64_t *count, double *avg_ms);
 
-/* Serving: continuous batching of solves that share (field, action, params)
- * into one multi-RHS batch, admission by HBM footprint, resident gauge fields.
- * A request is n_rhs columns; columns join and leave the running batch at
- * iteration boundaries.  b and x are host buffers owned by the caller until
- * the request completes; stats may be NULL. */
+/* Serving: continuous batching of propagator solves (the 12 spin-colour
+ * columns of sec. 2.1, the colour columns of sec. 2.2) on resident gauge
+ * fields.  A worker thread keeps one engine per (field, action, tol, sloppy
+ * precision, recon, reliable_delta); an engine holds up to max_cols columns
+ * (1..256) and advances all of them by one Krylov iteration per step, on its
+ * own stream, concurrently with the other engines.  Columns join at
+ * iteration boundaries when a slot is free and leave as soon as their FP64
+ * true residual meets tol.  A new engine is created only if its estimated
+ * HBM footprint fits hbm_budget (0: 80% of the free device memory at
+ * creation); idle engines are evicted least-recently-used first.  Requests
+ * are admitted in arrival order; one that does not fit yet waits without
+ * holding back later ones that do, and one whose engine alone exceeds the
+ * budget ends with LQ_ENOMEM.  Fields must outlive the server (destroy the
+ * server before lq_field_free).
+ *   Supported: LQ_TM_CLOVER (even-odd BiCGStab, sloppy 32 or 64, x = full
+ *   solution of D x = b) and LQ_HISQ with one mass m > 0 (mixed CG on
+ *   M_e = m^2 - D_eo D_oe, x = even-site solution, odd sites 0; as lq_solve
+ *   with reconstruct_full = 0).  Other kinds: LQ_ENOTSUP.
+ * b and x: host arrays [n_rhs][V][spin][colour] complex (as lq_solve), owned
+ * by the caller and left untouched (b) / not read (x) until the request is
+ * done; stats (may be NULL) is filled when it is done (iters = max over its
+ * columns, seconds = latency from submit).  n_rhs must be <= max_cols.
+ * lq_wait blocks until done and returns the request's status (LQ_OK,
+ * LQ_ENOCONV, or the error that ended it); lq_poll sets *done without
+ * blocking.  Tickets stay valid until lq_server_destroy, which finishes the
+ * queued and running requests first.  lq_server_stats: median and 99th
+ * percentile latency (seconds) of finished requests and columns finished per
+ * second since the first submit. */
 lq_status lq_server_create(lq_ctx *ctx, size_t hbm_budget, int max_cols, lq_server **srv);
 lq_status lq_server_destroy(lq_server *srv);
 lq_status lq_submit(lq_server *srv, const lq_action *act, const lq_field *g, const lq_params *prm, int n_rhs,

@@ -318,6 +318,7 @@ lq_status lq_copy_bandwidth(lq_ctx* c, size_t bytes, int reps, double* gbs) {
 
 lq_status lq_profile(lq_ctx* c, int enable) {
   if (!c) return (lq_status)fail(LQ_EINVAL, "ctx is NULL");
+  std::lock_guard<std::recursive_mutex> lk(c->prof_mtx);
   prof_flush(c);
   if (enable) c->totals.clear();
   c->prof = enable != 0;
@@ -326,6 +327,7 @@ lq_status lq_profile(lq_ctx* c, int enable) {
 
 lq_status lq_profile_get(lq_ctx* c, const char* name, int64_t* count, double* avg_ms) {
   if (!c || !name || !count || !avg_ms) return (lq_status)fail(LQ_EINVAL, "NULL argument");
+  std::lock_guard<std::recursive_mutex> lk(c->prof_mtx);
   prof_flush(c);
   auto it = c->totals.find(name);
   if (it == c->totals.end()) {

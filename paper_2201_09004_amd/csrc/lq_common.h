@@ -91,11 +91,6 @@ __device__ __forceinline__ int nb_cb(const int c[4], int mu, int k, const Geom& 
   return coords_cb(d, g);
 }
 
-// compiler scheduling fence (no instruction moves across it)
-#ifndef LQ_SCHED_FENCE
-#define LQ_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
-#endif
-
 // ---------------------------------------------------------------- fields
 #ifndef LQ_TILE
 #define LQ_TILE 8
@@ -330,8 +325,11 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // Launch shape knobs (tuned): sh = gw | tpb << 8 | xcd << 16 with gw column
 // groups and tpb site tiles per workgroup (one wave each), xcd = 1 to apply
 // xcd_remap to the block index.
-__device__ __forceinline__ bool stencil_site(const Geom& g, int par_out, int bz, int ngrp, int sh, int& par, int& cb,
-                                             int& grp, int c[4]) {
+// Returns 0 when the whole wave has no sites (it can exit), 1 for a lane with
+// a site, 2 for a lane of the last, partial tile past the end (its site is
+// clamped to the last one so that it can still join wave-wide reductions).
+__device__ __forceinline__ int stencil_site(const Geom& g, int par_out, int bz, int ngrp, int sh, int& par, int& cb,
+                                            int& grp, int c[4], int* tile_out = nullptr) {
   const int nsite = par_out == 2 ? 2 * g.Vh : g.Vh;
   const int ntile = (nsite + 63) >> 6;
   const int gw = sh & 0xff, tpb = (sh >> 8) & 0xff;
@@ -343,7 +341,7 @@ __device__ __forceinline__ bool stencil_site(const Geom& g, int par_out, int bz,
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = bt * tpb + w / gw;
   grp = (lb - bt * nchunk) * gw + (w % gw);
-  const int j = tile * 64 + (threadIdx.x & 63);
+  int j = tile * 64 + (threadIdx.x & 63);
   // Waves past the last column group (grp >= ngrp, when gw does not divide
   // ngrp) are not turned away here: the kernels give them no columns
   // (ncol - grp*NR <= 0), so they only read valid addresses and store
@@ -351,7 +349,10 @@ __device__ __forceinline__ bool stencil_site(const Geom& g, int par_out, int bz,
   // guard true and merge the whole stencil into one block, which doubles
   // register use and spills.
   (void)ngrp;
-  if (tile >= ntile || j >= nsite) return false;
+  if (tile >= ntile) return 0;
+  if (tile_out) *tile_out = tile;
+  const int status = j < nsite ? 1 : 2;
+  if (j >= nsite) j = nsite - 1;
   par = par_out == 2 ? (j >= g.Vh ? 1 : 0) : par_out;
   const int jj = par_out == 2 ? j - par * g.Vh : j;
   const int xh = jj % g.Lxh;
@@ -369,12 +370,12 @@ __device__ __forceinline__ bool stencil_site(const Geom& g, int par_out, int bz,
   }
   c[0] = 2 * xh + ((c[1] + c[2] + c[3] + par) & 1);
   cb = xh + g.Lxh * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
-  return true;
+  return status;
 }
 
 // launch shape matching stencil_site: 64 sites x gw groups per workgroup, at
-// most 8 waves (the kernels declare 512-thread launch bounds so that the
-// register-blocked variants keep up to 256 VGPRs without spilling)
+// most 4 waves (256-thread launch bounds leave the register-blocked variants
+// up to 256 VGPRs)
 constexpr int kStencilMaxThreads = 256;
 struct StencilGrid {
   int blocks, threads, sh;

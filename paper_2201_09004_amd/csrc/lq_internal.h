@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <functional>
 #include <map>
@@ -41,13 +42,14 @@ struct Shape {
 struct lq_ctx {
   int device = 0;
   hipStream_t stream = nullptr;  // stream of the host-pointer API
-  bool prof = false;
+  std::atomic<bool> prof{false};
   std::vector<lq::ProfRec> pending;
   std::vector<hipEvent_t> event_pool;
   std::map<std::string, std::pair<int64_t, double>> totals;
   double* partial = nullptr;  // reduction partials
   size_t partial_bytes = 0;
   std::mutex mtx;
+  std::recursive_mutex prof_mtx;  // kernel timing records (shared by API threads and the server worker)
   // autotuned launch shapes per kernel key
   std::map<std::string, lq::Shape> tune;
   bool tune_loaded = false;
@@ -157,7 +159,10 @@ const Clover* get_clover(OpEnv& e);
 int wilson_D(OpEnv& e, int prec, Vec& out, const Vec& in, bool dag);
 int wilson_hop(OpEnv& e, int prec, Vec& out, const Vec& in);
 int tm_site(OpEnv& e, int prec, Vec& out, const Vec& in, bool inverse);
-int tm_schur(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o);
+// red_mode 1: fused <rh, out> partials, 2: fused <out, in>, |out|^2 partials
+// written to red as [col][64-site tiles of Vh][4] (see EPI_XMY_RDOT / EPI_XMY_RTS)
+int tm_schur(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o, int red_mode = 0, double* red = nullptr,
+             const Vec* rh = nullptr);
 int tm_schur_source(OpEnv& e, Vec& bhat_e, const Vec& b);                 // FP64
 int tm_schur_reconstruct(OpEnv& e, Vec& x, const Vec& x_e, const Vec& b); // FP64, x full
 // overlap

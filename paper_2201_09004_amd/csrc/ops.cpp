@@ -14,6 +14,7 @@ namespace lq {
 // ------------------------------------------------------------------ timing
 Prof::Prof(lq_ctx* ctx, const char* name, hipStream_t st) : c(ctx), s(st) {
   if (!c || !c->prof) return;
+  std::lock_guard<std::recursive_mutex> lk(c->prof_mtx);
   hipEvent_t ev[2];
   for (int k = 0; k < 2; ++k) {
     if (!c->event_pool.empty()) {
@@ -29,10 +30,12 @@ Prof::Prof(lq_ctx* ctx, const char* name, hipStream_t st) : c(ctx), s(st) {
 }
 Prof::~Prof() {
   if (idx < 0) return;
+  std::lock_guard<std::recursive_mutex> lk(c->prof_mtx);
   hipEventRecord(c->pending[idx].b, s);
   if (c->pending.size() > 8192) prof_flush(c);
 }
 void prof_flush(lq_ctx* c) {
+  std::lock_guard<std::recursive_mutex> lk(c->prof_mtx);
   for (auto& r : c->pending) {
     hipEventSynchronize(r.b);
     float ms = 0.f;
@@ -116,7 +119,15 @@ FieldRef Vec::cols(int c0) const {
   return r;
 }
 
-int vec_zero(Vec& v) { return v.ncol ? launch_fill_zero(v.f.data, v.bytes, v.s) : 0; }
+// zeroes the columns (and FP16 norms) that v covers; works on views
+int vec_zero(Vec& v) {
+  if (!v.ncol) return 0;
+  const size_t nblk = (size_t)v.ncol * v.npar;
+  if (launch_fill_zero(v.f.data, nblk * block_bytes(v.prec, v.nc, v.f.Vh), v.s) ||
+      (v.f.norm && launch_fill_zero(v.f.norm, nblk * v.f.Vh * sizeof(float), v.s)))
+    return fail(LQ_EDEVICE, "zero fill");
+  return 0;
+}
 
 int vec_copy(Vec& dst, const Vec& src) {
   if (dst.ncol != src.ncol || dst.npar != src.npar || dst.nc != src.nc) return fail(LQ_EINVAL, "vec_copy: shape");
@@ -146,7 +157,8 @@ int ensure_links(OpEnv& e, int prec) {
     void* p = nullptr;
     if (hipMalloc(&p, esz * ne * 8 * (size_t)f->g.Vh) != hipSuccess) return fail(LQ_ENOMEM, "link allocation");
     int r = launch_pack_links(f->g, f->aos, p, prec, ne, 0, 1.0, e.s);
-    if (r) return fail(LQ_EDEVICE, "pack links");
+    // complete before publishing: other streams (server engines, API calls) may use the field next
+    if (r || hipStreamSynchronize(e.s) != hipSuccess) return fail(LQ_EDEVICE, "pack links");
     f->links[pi][rc] = p;
     return 0;
   }
@@ -164,7 +176,7 @@ int ensure_links(OpEnv& e, int prec) {
   if (hipMalloc(&pf, bytes) != hipSuccess || hipMalloc(&pl, bytes) != hipSuccess)
     return fail(LQ_ENOMEM, "HISQ link allocation");
   if (launch_pack_links(f->g, f->aos, pf, prec, 9, 1, sf, e.s) ||
-      launch_pack_links(f->g, f->aos2, pl, prec, 9, 3, sl, e.s))
+      launch_pack_links(f->g, f->aos2, pl, prec, 9, 3, sl, e.s) || hipStreamSynchronize(e.s) != hipSuccess)
     return fail(LQ_EDEVICE, "pack HISQ links");
   f->fat[pi] = pf;
   f->lng[pi] = pl;
@@ -185,20 +197,22 @@ int ensure_clover(OpEnv& e, int prec) {
   if (!c.H[0]) {
     if (hipMalloc(&c.H[0], nH * 16) != hipSuccess || hipMalloc(&c.Ainv[0], nA * 16) != hipSuccess)
       return fail(LQ_ENOMEM, "clover allocation");
-    if (launch_clover_build(f->g, f->links[0][0], e.act.c_sw, e.act.m, e.act.mu, c.H[0], c.Ainv[0], e.s))
+    if (launch_clover_build(f->g, f->links[0][0], e.act.c_sw, e.act.m, e.act.mu, c.H[0], c.Ainv[0], e.s) ||
+        hipStreamSynchronize(e.s) != hipSuccess)
       return fail(LQ_EDEVICE, "clover build");
   }
   if (prec == 32 && !c.H[1]) {
     if (hipMalloc(&c.H[1], nH * 8) != hipSuccess || hipMalloc(&c.Ainv[1], nA * 8) != hipSuccess)
       return fail(LQ_ENOMEM, "clover allocation");
     if (launch_clover_convert(c.H[0], c.H[1], (int64_t)nH, e.s) ||
-        launch_clover_convert(c.Ainv[0], c.Ainv[1], (int64_t)nA, e.s))
+        launch_clover_convert(c.Ainv[0], c.Ainv[1], (int64_t)nA, e.s) || hipStreamSynchronize(e.s) != hipSuccess)
       return fail(LQ_EDEVICE, "clover convert");
   }
   return 0;
 }
 
 const Clover* get_clover(OpEnv& e) {
+  std::lock_guard<std::mutex> lk(e.f->mtx);  // map nodes are stable; lookups race with inserts only
   auto it = e.f->clover.find(std::make_tuple(e.act.m, e.act.c_sw, e.act.mu));
   return it == e.f->clover.end() ? nullptr : &it->second;
 }
@@ -354,13 +368,14 @@ static int run_wilson(OpEnv& e, WilsonArgs& A, int n_fields, int clov_mats, int 
   A.recon = (e.recon && A.prec != 64) ? 1 : 0;
   if (!A.links) return fail(LQ_EDEVICE, "links not packed");
   const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
-  static const char* epi_names[] = {"hop", "xpay", "xpay_g5", "clovinv", "xmy", "site", "cheb"};
+  static const char* epi_names[] = {"hop", "xpay", "xpay_g5", "clovinv", "xmy", "site", "cheb", "xmyd", "xmyt"};
   char name[48];
   snprintf(name, sizeof(name), "wilson%d_%s", A.prec, epi_names[A.epi]);
   char key[160];
   snprintf(key, sizeof(key), "%s_r%d_d%d_n%d_v%d_p%d", name, A.recon, A.dag, A.ncol, A.g.Vh, A.par_out);
   const bool blocked = !A.dag && (A.epi == EPI_CLOVINV || A.epi == EPI_XMY_CLOVINV || A.epi == EPI_XPAY ||
-                                  A.epi == EPI_XPAY_G5 || A.epi == EPI_CHEB);
+                                  A.epi == EPI_XPAY_G5 || A.epi == EPI_CHEB || A.epi == EPI_XMY_RDOT ||
+                                  A.epi == EPI_XMY_RTS);
   const int out_npar = A.out.npar;
   Prof p(e.ctx, name, e.s);
   int r = tuned(e.ctx, key, A, tune_out_bytes(A.prec, 12, A.ncol, out_npar, A.g.Vh), A.prec,
@@ -425,7 +440,8 @@ int tm_site(OpEnv& e, int prec, Vec& out, const Vec& in, bool inverse) {
   return r ? fail(LQ_EDEVICE, "site kernel") : 0;
 }
 
-int tm_schur(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o) {
+int tm_schur(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o, int red_mode, double* red,
+             const Vec* rh) {
   int r = ensure_links(e, prec);
   if (!r) r = ensure_clover(e, prec);
   if (r) return r;
@@ -447,6 +463,17 @@ int tm_schur(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o) {
   A.x = in_e.f;
   A.par_out = 0;
   A.epi = EPI_XMY_CLOVINV;
+  if (red_mode == 1 && red && rh) {
+    A.epi = EPI_XMY_RDOT;
+    A.red = red;
+    A.rh = rh->f;
+    return run_wilson(e, A, 4, 2, 648);
+  }
+  if (red_mode == 2 && red) {
+    A.epi = EPI_XMY_RTS;
+    A.red = red;
+    return run_wilson(e, A, 3, 2, 672);
+  }
   return run_wilson(e, A, 3, 2, 600);
 }
 

@@ -1,0 +1,62 @@
+// Host helpers shared by the Krylov drivers and the serving engines:
+// pinned host buffers, device-resident per-column solver state with its host
+// mirror, per-column norms and FP64 true residuals.
+#pragma once
+
+#include <algorithm>
+#include <functional>
+#include <vector>
+
+#include "lq_internal.h"
+
+namespace lq {
+
+struct HostPinned {
+  double* p = nullptr;
+  explicit HostPinned(size_t n) {
+    if (hipHostMalloc((void**)&p, n * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+  }
+  HostPinned(const HostPinned&) = delete;
+  HostPinned& operator=(const HostPinned&) = delete;
+  ~HostPinned() {
+    if (p) hipHostFree(p);
+  }
+};
+
+// per-column solver state [ncol][ST_STRIDE] on the device and in pinned host memory
+struct State {
+  DBuf dev;
+  HostPinned host;
+  int ncol;
+  hipStream_t s;
+  State(int n, hipStream_t st)
+      : dev((size_t)std::max(n, 1) * ST_STRIDE * 8, st), host((size_t)std::max(n, 1) * ST_STRIDE), ncol(n), s(st) {}
+  bool ok() const { return dev.p && host.p; }
+  double* d() { return dev.as<double>(); }
+  double& h(int col, int k) { return host.p[col * ST_STRIDE + k]; }
+  int pull(int n = -1) {
+    const size_t cnt = (size_t)(n < 0 ? ncol : n) * ST_STRIDE * 8;
+    if (hipMemcpyAsync(host.p, dev.p, cnt, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(LQ_EDEVICE, "state readback");
+    return 0;
+  }
+  int push(int n = -1) {
+    const size_t cnt = (size_t)(n < 0 ? ncol : n) * ST_STRIDE * 8;
+    if (hipMemcpyAsync(dev.p, host.p, cnt, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(LQ_EDEVICE, "state upload");
+    return 0;
+  }
+};
+
+using OpFn = std::function<int(Vec& out, const Vec& in)>;
+
+// per-column |v|^2 (host vector)
+int col_norms(Blas& bl, Vec& v, std::vector<double>& out);
+// per-column relative residual |b - A x| / |b| in FP64
+int rel_residual(Blas& bl, const OpFn& A, Vec& x, Vec& b, std::vector<double>& res, const Geom& g);
+
+}  // namespace lq

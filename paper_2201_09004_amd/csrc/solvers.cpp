@@ -14,54 +14,18 @@
 #include <random>
 
 #include "lq_internal.h"
+#include "solver_util.h"
 
 namespace lq {
 
+
 namespace {
-
-struct HostPinned {
-  double* p = nullptr;
-  explicit HostPinned(size_t n) {
-    if (hipHostMalloc((void**)&p, n * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-    }
-  }
-  ~HostPinned() {
-    if (p) hipHostFree(p);
-  }
-};
-
-struct State {
-  DBuf dev;
-  HostPinned host;
-  int ncol;
-  hipStream_t s;
-  State(int n, hipStream_t st) : dev((size_t)std::max(n, 1) * ST_STRIDE * 8, st), host((size_t)std::max(n, 1) * ST_STRIDE), ncol(n), s(st) {}
-  bool ok() const { return dev.p && host.p; }
-  double* d() { return dev.as<double>(); }
-  double& h(int col, int k) { return host.p[col * ST_STRIDE + k]; }
-  int pull() {
-    if (hipMemcpyAsync(host.p, dev.p, (size_t)ncol * ST_STRIDE * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return fail(LQ_EDEVICE, "state readback");
-    return 0;
-  }
-  int push() {
-    if (hipMemcpyAsync(dev.p, host.p, (size_t)ncol * ST_STRIDE * 8, hipMemcpyHostToDevice, s) != hipSuccess)
-      return fail(LQ_EDEVICE, "state upload");
-    return 0;
-  }
-};
-
-using OpFn = std::function<int(Vec& out, const Vec& in)>;
-
 struct Counters {
   int iters = 0, reliable = 0, restarts = 0;
   int fault = 0;
 };
+}  // namespace
 
-// per-column |v|^2 (host vector)
 int col_norms(Blas& bl, Vec& v, std::vector<double>& out) {
   State st(v.ncol, bl.s);
   if (!st.ok()) return fail(LQ_ENOMEM, "state");
@@ -74,7 +38,6 @@ int col_norms(Blas& bl, Vec& v, std::vector<double>& out) {
   return 0;
 }
 
-// per-column relative residual |b - A x| / |b| in FP64
 int rel_residual(Blas& bl, const OpFn& A, Vec& x, Vec& b, std::vector<double>& res, const Geom& g) {
   Vec q = make_vec(g, 64, b.nc, b.ncol, b.npar, b.par0, bl.s);
   if (!q.ok()) return fail(LQ_ENOMEM, "residual buffer");
@@ -90,6 +53,8 @@ int rel_residual(Blas& bl, const OpFn& A, Vec& x, Vec& b, std::vector<double>& r
   for (int c = 0; c < b.ncol; ++c) res[c] = bb[c] > 0 ? std::sqrt(st.h(c, ST_RR) / bb[c]) : 0.0;
   return 0;
 }
+
+namespace {
 
 // Mixed-precision CG with reliable updates on a Hermitian positive-definite A.
 // x, b: FP64.  Columns stop when the FP64 residual of A meets tol[c] |b_c|.
@@ -191,10 +156,18 @@ int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int pl
 }
 
 // Mixed-precision BiCGStab with reliable updates for a non-Hermitian M.
+// M_fused (optional): the sloppy operator with fused reductions (mode 1:
+// <rh, out>, mode 2: <out, in> and |out|^2) as partials over 64-site tiles.
+using FusedFn = std::function<int(Vec& out, const Vec& in, int mode, double* red, const Vec* rh)>;
+
 int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int plo, Vec& x, Vec& b,
-                   const std::vector<double>& tol, int maxiter, double delta, Counters& cnt) {
+                   const std::vector<double>& tol, int maxiter, double delta, Counters& cnt,
+                   const FusedFn* M_fused = nullptr) {
   const int n = b.ncol, nc = b.nc, npar = b.npar, par0 = b.par0;
   hipStream_t s = bl.s;
+  const int fused_tiles = (npar * g.Vh + 63) / 64;
+  DBuf redbuf(M_fused ? sizeof(double) * 4 * (size_t)fused_tiles * n : 0, s);
+  if (M_fused && !redbuf.p) return fail(LQ_ENOMEM, "reduction partials");
   Vec r = make_vec(g, 64, nc, n, npar, par0, s);
   Vec q64 = make_vec(g, 64, nc, n, npar, par0, s);
   Vec rs = make_vec(g, plo, nc, n, npar, par0, s);
@@ -245,13 +218,27 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
   bool dirty = false;
   int it = 0;
   for (; it < maxiter && nactive > 0; ++it) {
-    if ((e = M_lo(v, p))) return e;
-    if ((e = bl.op(OP_DOT, &rhat, &v))) return e;
-    if (launch_scalar(SC_BICG_ALPHA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if (M_fused) {
+      // <rhat, v> computed by the stencil that produces v
+      if ((e = (*M_fused)(v, p, 1, redbuf.as<double>(), &rhat))) return e;
+      if (launch_scalar(SC_BICG_ALPHA, redbuf.as<double>(), fused_tiles, n, st.d(), s))
+        return fail(LQ_EDEVICE, "scalar");
+    } else {
+      if ((e = M_lo(v, p))) return e;
+      if ((e = bl.op(OP_DOT, &rhat, &v))) return e;
+      if (launch_scalar(SC_BICG_ALPHA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    }
     if ((e = bl.op(OP_AXMY, &v, &rs, nullptr, nullptr, nullptr, st.d(), ST_ALPHA, ST_ALPHA))) return e;
-    if ((e = M_lo(t, rs))) return e;
-    if ((e = bl.op(OP_DOT_NORM, &t, &rs))) return e;
-    if (launch_scalar(SC_BICG_OMEGA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if (M_fused) {
+      // <t, s> and |t|^2 computed by the stencil that produces t = M s
+      if ((e = (*M_fused)(t, rs, 2, redbuf.as<double>(), nullptr))) return e;
+      if (launch_scalar(SC_BICG_OMEGA, redbuf.as<double>(), fused_tiles, n, st.d(), s))
+        return fail(LQ_EDEVICE, "scalar");
+    } else {
+      if ((e = M_lo(t, rs))) return e;
+      if ((e = bl.op(OP_DOT_NORM, &t, &rs))) return e;
+      if (launch_scalar(SC_BICG_OMEGA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    }
     if ((e = bl.op(OP_BICG_XR, &p, &rs, &t, &xs, &rhat, st.d(), ST_ALPHA, ST_OMEGA))) return e;
     if (launch_scalar(SC_BICG_BETA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
     dirty = true;
@@ -365,9 +352,14 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
       if ((e = blas_prepare(c, ble, g, 1, n_rhs, s))) return e;
       OpFn M64 = [&](Vec& o, const Vec& i) { return tm_schur(env, 64, o, i, to64); };
       OpFn Mlo = [&](Vec& o, const Vec& i) { return tm_schur(env, plo, o, i, tolo); };
+      FusedFn Mfused = [&](Vec& o, const Vec& i, int mode, double* red, const Vec* rh) {
+        return tm_schur(env, plo, o, i, tolo, mode, red, rh);
+      };
+      const bool fuse = getenv("LQ_NO_FUSED_REDUCTIONS") == nullptr;
       std::vector<double> tol_s(n_rhs, 0.5 * tol);
       for (int pass = 0; pass < 6; ++pass) {
-        const int rs = bicgstab_mixed(ble, g, M64, Mlo, plo, xe, bh, tol_s, maxiter, delta, cnt);
+        const int rs = bicgstab_mixed(ble, g, M64, Mlo, plo, xe, bh, tol_s, maxiter, delta, cnt,
+                                      fuse ? &Mfused : nullptr);
         if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
         if ((e = tm_schur_reconstruct(env, x, xe, b))) return e;
         if ((e = rel_residual(bl, D64, x, b, res, g))) return e;

@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(kStencilMaxThreads) stag_kernel(StagArgs A) {
   using R = typename RealOf<P>::T;
   const int ngrp = (A.ncol + NR - 1) / NR;
   int par, cb, grp, c[4];
-  if (!stencil_site(A.g, A.par_out, A.slab, ngrp, A.sh, par, cb, grp, c)) return;
+  if (stencil_site(A.g, A.par_out, A.slab, ngrp, A.sh, par, cb, grp, c) != 1) return;
   const int col0 = grp * NR;
   const int nv = min(NR, A.ncol - col0);
   cx<R> af[NR][3], al[NR][3];

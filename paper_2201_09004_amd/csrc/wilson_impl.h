@@ -207,9 +207,14 @@ template <int P, int NE, bool DAG, int EPI, int NR>
 #endif
 __global__ void LQ_STENCIL_ATTR wilson_kernel(WilsonArgs A) {
   using R = typename RealOf<P>::T;
+  constexpr bool XMY = EPI == EPI_XMY_CLOVINV || EPI == EPI_XMY_RDOT || EPI == EPI_XMY_RTS;
+  constexpr int RED = EPI == EPI_XMY_RDOT ? 1 : EPI == EPI_XMY_RTS ? 2 : 0;
   const int ngrp = (A.ncol + NR - 1) / NR;
-  int par, cb, grp, c[4];
-  if (!stencil_site(A.g, A.par_out, A.slab, ngrp, A.sh, par, cb, grp, c)) return;
+  int par, cb, grp, c[4], tile = 0;
+  const int status = stencil_site(A.g, A.par_out, A.slab, ngrp, A.sh, par, cb, grp, c, &tile);
+  // lanes past the end of the last tile stay only to join the wave reductions
+  if (status == 0 || (RED == 0 && status != 1)) return;
+  const bool live = status == 1;
   const int col0 = grp * NR;
   const int nv = min(NR, A.ncol - col0);  // <= 0 for waves without columns
 
@@ -218,16 +223,10 @@ __global__ void LQ_STENCIL_ATTR wilson_kernel(WilsonArgs A) {
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int i = 0; i < 12; ++i) acc[r][i] = {0, 0};
-  // scheduling fences between directions: without them the scheduler hoists
-  // the loads of all eight hops into one block and runs out of registers
   hop_dir<P, NE, DAG, 0, NR>(A, c, par, cb, col0, nv, acc);
-  LQ_SCHED_FENCE();
   hop_dir<P, NE, DAG, 1, NR>(A, c, par, cb, col0, nv, acc);
-  LQ_SCHED_FENCE();
   hop_dir<P, NE, DAG, 2, NR>(A, c, par, cb, col0, nv, acc);
-  LQ_SCHED_FENCE();
   hop_dir<P, NE, DAG, 3, NR>(A, c, par, cb, col0, nv, acc);
-  LQ_SCHED_FENCE();
 
   const R k = (R)A.k_hop;
 #pragma unroll
@@ -235,10 +234,13 @@ __global__ void LQ_STENCIL_ATTR wilson_kernel(WilsonArgs A) {
 #pragma unroll
     for (int i = 0; i < 12; ++i) acc[r][i] = k * acc[r][i];
 
-  if constexpr (EPI == EPI_CLOVINV || EPI == EPI_XMY_CLOVINV) {
+  if constexpr (EPI == EPI_CLOVINV || XMY) {
     apply_full6_nr<P, NR>(A.clov_inv, A.g.Vh, par, 0, cb, nv, acc, 0);
     apply_full6_nr<P, NR>(A.clov_inv, A.g.Vh, par, 1, cb, nv, acc, 6);
   }
+  double red[NR][3];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[r][0] = red[r][1] = red[r][2] = 0.0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     if (r >= nv) continue;
@@ -247,11 +249,29 @@ __global__ void LQ_STENCIL_ATTR wilson_kernel(WilsonArgs A) {
     if constexpr (EPI == EPI_HOP || EPI == EPI_CLOVINV) {
 #pragma unroll
       for (int i = 0; i < 12; ++i) out[i] = acc[r][i];
-    } else if constexpr (EPI == EPI_XMY_CLOVINV) {
+    } else if constexpr (XMY) {
       cx<R> x[12];
       IO<P, 12>::load(A.x, blk_index(A.x, col, par), cb, x);
 #pragma unroll
       for (int i = 0; i < 12; ++i) out[i] = x[i] - acc[r][i];
+      if (live) {
+        if constexpr (RED == 1) {
+          cx<R> h[12];
+          IO<P, 12>::load(A.rh, blk_index(A.rh, col, par), cb, h);
+#pragma unroll
+          for (int i = 0; i < 12; ++i) {
+            red[r][0] += (double)h[i].re * (double)out[i].re + (double)h[i].im * (double)out[i].im;
+            red[r][1] += (double)h[i].re * (double)out[i].im - (double)h[i].im * (double)out[i].re;
+          }
+        } else if constexpr (RED == 2) {
+#pragma unroll
+          for (int i = 0; i < 12; ++i) {
+            red[r][0] += (double)out[i].re * (double)x[i].re + (double)out[i].im * (double)x[i].im;
+            red[r][1] += (double)out[i].re * (double)x[i].im - (double)out[i].im * (double)x[i].re;
+            red[r][2] += (double)out[i].re * (double)out[i].re + (double)out[i].im * (double)out[i].im;
+          }
+        }
+      }
     } else if constexpr (EPI == EPI_XPAY || EPI == EPI_XPAY_G5 || EPI == EPI_CHEB) {
       cx<R> x[12];
       IO<P, 12>::load(A.x, blk_index(A.x, col, par), cb, x);
@@ -286,7 +306,26 @@ __global__ void LQ_STENCIL_ATTR wilson_kernel(WilsonArgs A) {
 #pragma unroll
       for (int i = 6; i < 12; ++i) out[i] = out[i] - mu * times_i(x[i]) + acc[r][i];
     }
-    IO<P, 12>::store(A.out, blk_index(A.out, col, par), cb, out);
+    if (live) IO<P, 12>::store(A.out, blk_index(A.out, col, par), cb, out);
+  }
+  if constexpr (RED != 0) {
+    // wave butterfly (fixed order) and one partial per (column, 64-site tile)
+    const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
+    const int ntile = (nsite + 63) >> 6;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r >= nv) continue;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        for (int o = 32; o > 0; o >>= 1) red[r][k] += __shfl_xor(red[r][k], o);
+      if ((threadIdx.x & 63) == 0) {
+        double* p = A.red + ((int64_t)(col0 + r) * ntile + tile) * 4;
+        p[0] = red[r][0];
+        p[1] = red[r][1];
+        p[2] = red[r][2];
+        p[3] = 0.0;
+      }
+    }
   }
 }
 
@@ -302,7 +341,8 @@ inline void launch_one(const WilsonArgs& A, int bs, hipStream_t s) {
 
 // epilogues with register-blocked variants (NR > 1)
 constexpr bool epi_blocked(int epi) {
-  return epi == EPI_CLOVINV || epi == EPI_XMY_CLOVINV || epi == EPI_XPAY || epi == EPI_XPAY_G5 || epi == EPI_CHEB;
+  return epi == EPI_CLOVINV || epi == EPI_XMY_CLOVINV || epi == EPI_XPAY || epi == EPI_XPAY_G5 || epi == EPI_CHEB ||
+         epi == EPI_XMY_RDOT || epi == EPI_XMY_RTS;
 }
 
 template <int P, int NE, int EPI>
@@ -345,6 +385,8 @@ inline int launch_epi(const WilsonArgs& A, int nr, int bs, hipStream_t s) {
     switch (A.epi) {
       case EPI_CLOVINV: return launch_nr<P, NE, EPI_CLOVINV>(A, nr, bs, s);
       case EPI_XMY_CLOVINV: return launch_nr<P, NE, EPI_XMY_CLOVINV>(A, nr, bs, s);
+      case EPI_XMY_RDOT: return launch_nr<P, NE, EPI_XMY_RDOT>(A, nr, bs, s);
+      case EPI_XMY_RTS: return launch_nr<P, NE, EPI_XMY_RTS>(A, nr, bs, s);
       case EPI_SITE: return launch_nr<P, NE, EPI_SITE>(A, 1, bs, s);
       default: break;
     }

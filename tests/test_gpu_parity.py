@@ -226,8 +226,12 @@ def test_wilson_cgne_fp64(ctx):
         L.lq_field_free(f)
 
 
-@pytest.mark.parametrize("sloppy", [64, 32])
-def test_tm_clover_eo_bicgstab(ctx, sloppy):
+@pytest.mark.parametrize("sloppy,fused", [(64, True), (32, True), (32, False)])
+def test_tm_clover_eo_bicgstab(ctx, sloppy, fused, monkeypatch):
+    """Even-odd BiCGStab, with the BiCGStab reductions fused into the Schur
+    stencil epilogue or taken by separate BLAS kernels."""
+    if not fused:
+        monkeypatch.setenv("LQ_NO_FUSED_REDUCTIONS", "1")
     Lx = (4, 4, 6, 8)
     U, f = _wilson_setup(ctx, Lx, 91, eps=0.2)
     m, csw, mu = -0.0695, 1.0509, 0.01
