@@ -34,17 +34,23 @@ def _compile(src: str, build_dir: str, defines: list) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False, out: str = OUT, tile: int | None = None) -> str:
+def build(jobs: int | None = None, verbose: bool = False, out: str = OUT, tile: int | None = None,
+          defines: dict | None = None) -> str:
     """Compile every source and link `out`.  `tile` overrides the site-tile
-    width of the field layout (LQ_TILE; default 8, 1 = component planes)."""
-    defines = [] if tile is None else [f"-DLQ_TILE={int(tile)}"]
-    build_dir = BUILD if tile is None else os.path.join(BUILD, f"tile{int(tile)}")
+    width of the field layout (LQ_TILE; default 8, 1 = component planes);
+    `defines` adds preprocessor macros (e.g. {"LQ_NT": 0} for plain loads)."""
+    macros = dict(defines or {})
+    if tile is not None:
+        macros["LQ_TILE"] = int(tile)
+    flags = [f"-D{k}={v}" for k, v in sorted(macros.items())]
+    tag = "_".join(f"{k}{v}" for k, v in sorted(macros.items()))
+    build_dir = os.path.join(BUILD, tag) if tag else BUILD
     os.makedirs(build_dir, exist_ok=True)
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, build_dir, defines), srcs))
+        objs = list(ex.map(lambda s: _compile(s, build_dir, flags), srcs))
     tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", "-o", tmp] + objs + [f"--offload-arch={ARCH}", "-fPIC"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -237,9 +237,18 @@ __global__ void scalar_kernel(int op, const double* partial, int gridx, int ncol
   auto getc = [&](int off) { return cx<double>{s[off], s[off + 1]}; };
   switch (op) {
     case SC_CG_ALPHA: {
+      // <p, A p> <= 0 can only come from rounding in low-precision storage
+      // (A is positive definite): flag a restart of the column (flag 1) and
+      // take no step; a non-finite value is a numeric error (flag 2)
       const double pap = sum_r(p, gridx, 0);
       double a = s[ST_RR] / pap;
-      if (!isfinite(a)) { s[ST_FLAG] = 2; a = 0; }
+      if (!isfinite(pap)) {
+        s[ST_FLAG] = 2;
+        a = 0;
+      } else if (!(pap > 0.0) || !isfinite(a)) {
+        if (active) s[ST_FLAG] = 1;
+        a = 0;
+      }
       setc(ST_ALPHA, {active ? a : 0.0, 0.0});
       break;
     }
@@ -374,7 +383,17 @@ __global__ void ms_alpha_kernel(MsArgs A, const double* sigma) {
   double* s = A.st + (int64_t)j * ST_STRIDE;
   const double pap = sum_r(A.partial + (int64_t)j * A.gridx * 4, A.gridx, 0);
   double a = s[ST_RR] / pap;
-  if (!isfinite(a)) { a = 0; s[ST_FLAG] = 2; }
+  if (!isfinite(pap)) {
+    a = 0;
+    s[ST_FLAG] = 2;
+  } else if (!(pap > 0.0) || !isfinite(a)) {
+    // loss of positivity from low-precision rounding: stop the multi-shift
+    // stage for this right-hand side (its iterate stays a valid starting
+    // guess for the per-shift refinement)
+    a = 0;
+    s[ST_FLAG] = 1;
+    for (int i = 0; i < A.nshift; ++i) A.sh[((int64_t)i * A.nrhs + j) * 8 + MS_ACT] = 0.0;
+  }
   const bool base_active = A.sh[(int64_t)j * 8 + MS_ACT] != 0.0;
   if (!base_active) a = 0.0;
   s[ST_ALPHA] = a;

@@ -105,6 +105,59 @@ __host__ __device__ __forceinline__ int64_t tix(int64_t g, int k, int K, int cb,
 #endif
 }
 
+// ---------------------------------------------------------------- streaming access
+// Data that a stencil launch touches exactly once (links, site matrices, the
+// output site's own operands and its result) goes through ldx/stx<true>.
+// With LQ_NT set these carry the non-temporal hint, meant to leave L2 to the
+// neighbour spinors (each read by eight sites); on gfx950 the hinted build
+// measured 20-30% slower stencils, so the hint is off by default.
+#ifndef LQ_NT
+#define LQ_NT 0  // bit 0: streaming loads, bit 1: streaming stores (measured slower on gfx950)
+#endif
+template <bool NT, typename T>
+__device__ __forceinline__ T ldx(const T* p) {
+  if constexpr (NT && (LQ_NT & 1) && (sizeof(T) == 16 || sizeof(T) == 8 || sizeof(T) == 4)) {
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    typedef unsigned v2u __attribute__((ext_vector_type(2)));
+    T out;
+    if constexpr (sizeof(T) == 16) {
+      const v4u r = __builtin_nontemporal_load((const v4u*)p);
+      __builtin_memcpy(&out, &r, 16);
+    } else if constexpr (sizeof(T) == 8) {
+      const v2u r = __builtin_nontemporal_load((const v2u*)p);
+      __builtin_memcpy(&out, &r, 8);
+    } else {
+      const unsigned r = __builtin_nontemporal_load((const unsigned*)p);
+      __builtin_memcpy(&out, &r, 4);
+    }
+    return out;
+  } else {
+    return *p;
+  }
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void stx(T* p, const T& v) {
+  if constexpr (NT && (LQ_NT & 2) && (sizeof(T) == 16 || sizeof(T) == 8 || sizeof(T) == 4)) {
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    typedef unsigned v2u __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(T) == 16) {
+      v4u r;
+      __builtin_memcpy(&r, &v, 16);
+      __builtin_nontemporal_store(r, (v4u*)p);
+    } else if constexpr (sizeof(T) == 8) {
+      v2u r;
+      __builtin_memcpy(&r, &v, 8);
+      __builtin_nontemporal_store(r, (v2u*)p);
+    } else {
+      unsigned r;
+      __builtin_memcpy(&r, &v, 4);
+      __builtin_nontemporal_store(r, (unsigned*)p);
+    }
+  } else {
+    *p = v;
+  }
+}
+
 struct FieldRef {
   void* data;
   float* norm;  // FP16 only
@@ -120,54 +173,60 @@ template <int P, int NC> struct IO;
 
 template <int NC> struct IO<64, NC> {
   using R = double;
+  template <bool NT = false>
   static __device__ __forceinline__ void load(const FieldRef& f, int64_t blk, int cb, cx<R>* v) {
     const double2* p = (const double2*)f.data;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      double2 d = p[tix(blk, c, NC, cb, f.Vh)];
+      double2 d = ldx<NT>(p + tix(blk, c, NC, cb, f.Vh));
       v[c] = {d.x, d.y};
     }
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void store(const FieldRef& f, int64_t blk, int cb, const cx<R>* v) {
     double2* p = (double2*)f.data;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) p[tix(blk, c, NC, cb, f.Vh)] = make_double2(v[c].re, v[c].im);
+    for (int c = 0; c < NC; ++c) stx<NT>(p + tix(blk, c, NC, cb, f.Vh), make_double2(v[c].re, v[c].im));
   }
 };
 
 template <> struct IO<32, 12> {
   using R = float;
+  template <bool NT = false>
   static __device__ __forceinline__ void load(const FieldRef& f, int64_t blk, int cb, cx<R>* v) {
     const float4* p = (const float4*)f.data;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      float4 d = p[tix(blk, k, 6, cb, f.Vh)];
+      float4 d = ldx<NT>(p + tix(blk, k, 6, cb, f.Vh));
       v[2 * k] = {d.x, d.y};
       v[2 * k + 1] = {d.z, d.w};
     }
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void store(const FieldRef& f, int64_t blk, int cb, const cx<R>* v) {
     float4* p = (float4*)f.data;
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-      p[tix(blk, k, 6, cb, f.Vh)] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+      stx<NT>(p + tix(blk, k, 6, cb, f.Vh), make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im));
   }
 };
 
 template <> struct IO<32, 3> {
   using R = float;
+  template <bool NT = false>
   static __device__ __forceinline__ void load(const FieldRef& f, int64_t blk, int cb, cx<R>* v) {
     const float2* p = (const float2*)f.data;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      float2 d = p[tix(blk, c, 3, cb, f.Vh)];
+      float2 d = ldx<NT>(p + tix(blk, c, 3, cb, f.Vh));
       v[c] = {d.x, d.y};
     }
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void store(const FieldRef& f, int64_t blk, int cb, const cx<R>* v) {
     float2* p = (float2*)f.data;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) p[tix(blk, c, 3, cb, f.Vh)] = make_float2(v[c].re, v[c].im);
+    for (int c = 0; c < 3; ++c) stx<NT>(p + tix(blk, c, 3, cb, f.Vh), make_float2(v[c].re, v[c].im));
   }
 };
 
@@ -182,55 +241,65 @@ __device__ __forceinline__ float site_maxabs(const cx<float>* v) {
   return m;
 }
 
+// Site norm as stored for FP16: a site whose largest component is below the
+// smallest normal FP32 number is stored as zero, because 1/n would overflow
+// to infinity (and infinity times a zero component is NaN).  Such sites are
+// at least 2^-126 times smaller than any normal site of the field.
+__device__ __forceinline__ float fp16_site_norm(float n) { return n >= 1.17549435e-38f ? n : 0.f; }
+
 template <> struct IO<16, 12> {
   using R = float;
+  template <bool NT = false>
   static __device__ __forceinline__ void load(const FieldRef& f, int64_t blk, int cb, cx<R>* v) {
     const uint4* p = (const uint4*)f.data;
-    const float n = f.norm[blk * f.Vh + cb];
+    const float n = ldx<NT>(f.norm + blk * f.Vh + cb);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      uint4 d = p[tix(blk, k, 3, cb, f.Vh)];
+      uint4 d = ldx<NT>(p + tix(blk, k, 3, cb, f.Vh));
       unsigned w[4] = {d.x, d.y, d.z, d.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         v[4 * k + j] = {n * h2f((unsigned short)(w[j] & 0xffffu)), n * h2f((unsigned short)(w[j] >> 16))};
     }
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void store(const FieldRef& f, int64_t blk, int cb, const cx<R>* v) {
     uint4* p = (uint4*)f.data;
-    const float n = site_maxabs<12>(v);
+    const float n = fp16_site_norm(site_maxabs<12>(v));
     const float s = n > 0.f ? 1.0f / n : 0.f;
-    f.norm[blk * f.Vh + cb] = n;
+    stx<NT>(f.norm + blk * f.Vh + cb, n);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       unsigned w[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         w[j] = (unsigned)f2h(s * v[4 * k + j].re) | ((unsigned)f2h(s * v[4 * k + j].im) << 16);
-      p[tix(blk, k, 3, cb, f.Vh)] = make_uint4(w[0], w[1], w[2], w[3]);
+      stx<NT>(p + tix(blk, k, 3, cb, f.Vh), make_uint4(w[0], w[1], w[2], w[3]));
     }
   }
 };
 
 template <> struct IO<16, 3> {
   using R = float;
+  template <bool NT = false>
   static __device__ __forceinline__ void load(const FieldRef& f, int64_t blk, int cb, cx<R>* v) {
     const unsigned* p = (const unsigned*)f.data;
-    const float n = f.norm[blk * f.Vh + cb];
+    const float n = ldx<NT>(f.norm + blk * f.Vh + cb);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      unsigned w = p[tix(blk, c, 3, cb, f.Vh)];
+      unsigned w = ldx<NT>(p + tix(blk, c, 3, cb, f.Vh));
       v[c] = {n * h2f((unsigned short)(w & 0xffffu)), n * h2f((unsigned short)(w >> 16))};
     }
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void store(const FieldRef& f, int64_t blk, int cb, const cx<R>* v) {
     unsigned* p = (unsigned*)f.data;
-    const float n = site_maxabs<3>(v);
+    const float n = fp16_site_norm(site_maxabs<3>(v));
     const float s = n > 0.f ? 1.0f / n : 0.f;
-    f.norm[blk * f.Vh + cb] = n;
+    stx<NT>(f.norm + blk * f.Vh + cb, n);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      p[tix(blk, c, 3, cb, f.Vh)] = (unsigned)f2h(s * v[c].re) | ((unsigned)f2h(s * v[c].im) << 16);
+      stx<NT>(p + tix(blk, c, 3, cb, f.Vh), (unsigned)f2h(s * v[c].re) | ((unsigned)f2h(s * v[c].im) << 16));
   }
 };
 
@@ -255,21 +324,21 @@ __device__ __forceinline__ void load_link(const void* base, int Vh, int par, int
     const double2* p = (const double2*)base;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      double2 d = p[tix(g, e, NE, cb, Vh)];
+      double2 d = ldx<true>(p + tix(g, e, NE, cb, Vh));
       U[e] = {d.x, d.y};
     }
   } else if constexpr (P == 32) {
     const float2* p = (const float2*)base;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      float2 d = p[tix(g, e, NE, cb, Vh)];
+      float2 d = ldx<true>(p + tix(g, e, NE, cb, Vh));
       U[e] = {d.x, d.y};
     }
   } else {
     const unsigned* p = (const unsigned*)base;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      unsigned w = p[tix(g, e, NE, cb, Vh)];
+      unsigned w = ldx<true>(p + tix(g, e, NE, cb, Vh));
       U[e] = {h2f((unsigned short)(w & 0xffffu)), h2f((unsigned short)(w >> 16))};
     }
   }
@@ -359,17 +428,18 @@ __device__ __forceinline__ int stencil_site(const Geom& g, int par_out, int bz, 
   int r = jj / g.Lxh;
   c[1] = r % g.L[1];
   r /= g.L[1];
-  if (bz > 0) {
-    const int zi = r % bz;
-    r /= bz;
-    c[3] = r % g.L[3];
-    c[2] = (r / g.L[3]) * bz + zi;
-  } else {
-    c[2] = r % g.L[2];
-    c[3] = r / g.L[2];
-  }
-  c[0] = 2 * xh + ((c[1] + c[2] + c[3] + par) & 1);
-  cb = xh + g.Lxh * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+  // z and t as scalars, stored once: stores to c[2] / c[3] in both branches
+  // would be merged into one store through a selected pointer, which keeps
+  // the coordinate array in scratch memory
+  const int bzz = bz > 0 ? bz : g.L[2];
+  const int zi = r % bzz;
+  r /= bzz;
+  const int t = bz > 0 ? r % g.L[3] : r;
+  const int z = bz > 0 ? (r / g.L[3]) * bz + zi : zi;
+  c[2] = z;
+  c[3] = t;
+  c[0] = 2 * xh + ((c[1] + z + t + par) & 1);
+  cb = xh + g.Lxh * (c[1] + g.L[1] * (z + g.L[2] * t));
   return status;
 }
 

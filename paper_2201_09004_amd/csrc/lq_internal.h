@@ -113,6 +113,7 @@ Vec make_vec(const Geom& g, int prec, int nc, int ncol, int npar, int par0, hipS
 Vec view(const Vec& v, int c0, int n);  // non-owning view of columns [c0, c0+n)
 int vec_zero(Vec& v);
 int vec_copy(Vec& dst, const Vec& src);  // with precision conversion, same shape
+int vec_swap_cols(Vec& v, int a, int b);  // exchange columns a and b in place
 
 // scoped device buffer
 struct DBuf {
@@ -159,10 +160,9 @@ const Clover* get_clover(OpEnv& e);
 int wilson_D(OpEnv& e, int prec, Vec& out, const Vec& in, bool dag);
 int wilson_hop(OpEnv& e, int prec, Vec& out, const Vec& in);
 int tm_site(OpEnv& e, int prec, Vec& out, const Vec& in, bool inverse);
-// red_mode 1: fused <rh, out> partials, 2: fused <out, in>, |out|^2 partials
-// written to red as [col][64-site tiles of Vh][4] (see EPI_XMY_RDOT / EPI_XMY_RTS)
-int tm_schur(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o, int red_mode = 0, double* red = nullptr,
-             const Vec* rh = nullptr);
+// red_mode 2: the partials of <out, in> and |out|^2 are written to red as
+// [col][64-site tiles of Vh][4] by the second stencil (EPI_XMY_RTS)
+int tm_schur(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o, int red_mode = 0, double* red = nullptr);
 int tm_schur_source(OpEnv& e, Vec& bhat_e, const Vec& b);                 // FP64
 int tm_schur_reconstruct(OpEnv& e, Vec& x, const Vec& x_e, const Vec& b); // FP64, x full
 // overlap

@@ -11,11 +11,10 @@
 namespace lq {
 
 // ------------------------------------------------------------ Wilson type
-// EPI_XMY_RDOT / EPI_XMY_RTS: EPI_XMY_CLOVINV plus per-column reductions of the
-// output written as wave partials red[(col * ntile + tile) * 4 + k]
-// (ntile = 64-site tiles of the launch): RDOT <rh, out>; RTS <out, x>, |out|^2.
-enum { EPI_HOP = 0, EPI_XPAY, EPI_XPAY_G5, EPI_CLOVINV, EPI_XMY_CLOVINV, EPI_SITE, EPI_CHEB, EPI_XMY_RDOT,
-       EPI_XMY_RTS };
+// EPI_XMY_RTS: EPI_XMY_CLOVINV plus the per-column reductions <out, x> and
+// |out|^2 written as wave partials red[(col * ntile + tile) * 4 + k]
+// (ntile = 64-site tiles of the launch).
+enum { EPI_HOP = 0, EPI_XPAY, EPI_XPAY_G5, EPI_CLOVINV, EPI_XMY_CLOVINV, EPI_SITE, EPI_CHEB, EPI_XMY_RTS };
 
 struct WilsonArgs {
   Geom g;
@@ -32,8 +31,7 @@ struct WilsonArgs {
   const void* clov_inv;  // full complex A^{-1} per chirality
   const double* acol;    // per-column coefficient of x (or nullptr: use a)
   double a, k_hop, mu_tw, s1, ck, s2;
-  double* red;           // fused-reduction partials (EPI_XMY_RDOT / EPI_XMY_RTS)
-  FieldRef rh;           // second operand of EPI_XMY_RDOT
+  double* red;           // fused-reduction partials (EPI_XMY_RTS)
 };
 int launch_wilson(const WilsonArgs& A, hipStream_t s);
 template <int P>
@@ -141,5 +139,7 @@ int launch_ms_init(const MsArgs& A, hipStream_t s);
 // profiling-free utilities
 int launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 int launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+// exchange two non-overlapping byte ranges of equal length (16-byte aligned)
+int launch_swap_bytes(void* a, void* b, size_t bytes, hipStream_t s);
 
 }  // namespace lq

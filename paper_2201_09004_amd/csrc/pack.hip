@@ -280,6 +280,32 @@ int launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+__global__ void swap_bytes_kernel(uint4* a, uint4* b, int64_t n16, unsigned char* ta, unsigned char* tb, int ntail) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) {
+    const uint4 x = a[i], y = b[i];
+    a[i] = y;
+    b[i] = x;
+  }
+  if (i < ntail) {
+    const unsigned char x = ta[i], y = tb[i];
+    ta[i] = y;
+    tb[i] = x;
+  }
+}
+
+int launch_swap_bytes(void* a, void* b, size_t bytes, hipStream_t s) {
+  if (bytes == 0 || a == b) return 0;
+  const int64_t n16 = (int64_t)(bytes / 16);
+  const int ntail = (int)(bytes % 16);
+  const int64_t n = n16 > ntail ? n16 : ntail;
+  const int bs = 256;
+  swap_bytes_kernel<<<(int)((n + bs - 1) / bs), bs, 0, s>>>((uint4*)a, (uint4*)b, n16,
+                                                            (unsigned char*)a + n16 * 16,
+                                                            (unsigned char*)b + n16 * 16, ntail);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
 }  // namespace lq
 
 namespace lq {

@@ -214,10 +214,11 @@ class TmEngine : public Engine {
     Vec tov = view(tolo, 0, w);
     int e = 0;
     double* rb = red.as<double>();
-    if ((e = tm_schur(*env, plo, vv, pv, tov, 1, rb, &rh))) return e;
-    if (launch_scalar(SC_BICG_ALPHA, rb, tiles, w, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if ((e = tm_schur(*env, plo, vv, pv, tov))) return e;
+    if ((e = ble.op(OP_DOT, &rh, &vv))) return e;
+    if (launch_scalar(SC_BICG_ALPHA, ble.partial, ble.gridx, w, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
     if ((e = ble.op(OP_AXMY, &vv, &rv, nullptr, nullptr, nullptr, st.d(), ST_ALPHA, ST_ALPHA))) return e;
-    if ((e = tm_schur(*env, plo, tv, rv, tov, 2, rb, nullptr))) return e;
+    if ((e = tm_schur(*env, plo, tv, rv, tov, 2, rb))) return e;
     if (launch_scalar(SC_BICG_OMEGA, rb, tiles, w, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
     if ((e = ble.op(OP_BICG_XR, &pv, &rv, &tv, &xsv, &rh, st.d(), ST_ALPHA, ST_OMEGA))) return e;
     if (launch_scalar(SC_BICG_BETA, ble.partial, ble.gridx, w, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
@@ -231,7 +232,8 @@ class TmEngine : public Engine {
     State& st = *stp;
     if (hipStreamSynchronize(s) != hipSuccess) return fail(LQ_EDEVICE, "engine step");
     last_used = Clock::now();
-    bool update = false, breakdown = false;
+    bool breakdown = false;
+    UpdateRule rule;
     for (int c = 0; c < w; ++c) {
       ColMeta& m = cols[c];
       ++m.iters;
@@ -239,8 +241,10 @@ class TmEngine : public Engine {
       if (st.h(c, ST_FLAG) == 1.0) breakdown = true;
       const double rr = st.h(c, ST_RR);
       m.maxrr = std::max(m.maxrr, rr);
-      if (rr < delta * delta * m.maxrr || rr < m.tol * m.tol * m.bb || m.iters >= maxiter) update = true;
+      rule.column(rr, m.maxrr, m.tol * m.tol * m.bb, delta);
+      if (m.iters >= maxiter) rule.now = true;
     }
+    const bool update = rule.fire();
     Vec pv = view(p, 0, w), vv = view(v, 0, w), rv = view(rs, 0, w), xsv = view(xs, 0, w), rh = view(rhat, 0, w),
         xv = view(xe, 0, w), rr64 = view(r64, 0, w), bh = view(bhat, 0, w), to = view(to64, 0, w);
     int e = 0;
@@ -405,15 +409,19 @@ class HisqEngine : public Engine {
     State& st = *stp;
     if (hipStreamSynchronize(s) != hipSuccess) return fail(LQ_EDEVICE, "engine step");
     last_used = Clock::now();
-    bool update = false;
+    UpdateRule rule;
+    std::vector<int> restart;  // columns that took no step (alpha = 0): p = r next
     for (int c = 0; c < w; ++c) {
       ColMeta& m = cols[c];
       ++m.iters;
       if (st.h(c, ST_FLAG) == 2.0 || !std::isfinite(st.h(c, ST_RR))) return fail(LQ_ENUMERIC, "NaN/Inf residual");
+      if (st.h(c, ST_FLAG) == 1.0) restart.push_back(c);
       const double rr = st.h(c, ST_RR);
       m.maxrr = std::max(m.maxrr, rr);
-      if (rr < delta * delta * m.maxrr || rr < m.tol * m.tol * m.bb || m.iters >= maxiter) update = true;
+      rule.column(rr, m.maxrr, m.tol * m.tol * m.bb, delta);
+      if (m.iters >= maxiter) rule.now = true;
     }
+    const bool update = rule.fire();
     Vec pv = view(p, 0, w), rv = view(rs, 0, w), xsv = view(xs, 0, w), yv = view(y, 0, w), bv = view(be, 0, w),
         rr64 = view(r64, 0, w), to = view(to64, 0, w);
     int e = 0;
@@ -431,6 +439,13 @@ class HisqEngine : public Engine {
         m.maxrr = st.h(c, ST_RR);
         if (st.h(c, ST_RR) <= m.tol * m.tol * m.bb || m.iters >= maxiter) finished.push_back(c);
       }
+    }
+    if (!restart.empty()) {
+      for (int c : restart) {
+        st.h(c, ST_FLAG) = 0.0;
+        st.h(c, ST_BETA) = 0.0;
+      }
+      if ((e = st.push(w))) return e;
     }
     if ((e = ble.op(OP_XPAY, &rv, &pv, nullptr, nullptr, nullptr, st.d(), ST_BETA, ST_BETA))) return e;
     std::sort(finished.rbegin(), finished.rend());

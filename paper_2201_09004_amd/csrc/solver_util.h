@@ -54,6 +54,24 @@ struct State {
 
 using OpFn = std::function<int(Vec& out, const Vec& in)>;
 
+// Reliable-update trigger for a batch of columns.  A column is due once its
+// iterated residual has dropped by delta since the last update; the batch
+// recomputes its FP64 residuals when a column may have converged, when one
+// column has dropped by delta^2 (its recursion error is then about the
+// sloppy precision times 1/delta^2 of its residual), or when half of the
+// active columns are due.  One update then serves every column.
+struct UpdateRule {
+  int due = 0, active = 0;
+  bool now = false;
+  void column(double rr, double maxrr, double tol2bb, double delta) {
+    ++active;
+    const double d2 = delta * delta;
+    if (rr < tol2bb || rr < d2 * d2 * maxrr) now = true;
+    else if (rr < d2 * maxrr) ++due;
+  }
+  bool fire() const { return now || (active > 0 && 2 * due >= active); }
+};
+
 // per-column |v|^2 (host vector)
 int col_norms(Blas& bl, Vec& v, std::vector<double>& out);
 // per-column relative residual |b - A x| / |b| in FP64

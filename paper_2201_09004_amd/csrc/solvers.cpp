@@ -56,10 +56,28 @@ int rel_residual(Blas& bl, const OpFn& A, Vec& x, Vec& b, std::vector<double>& r
 
 namespace {
 
+// Per-column parameters of the operator (e.g. one mass per column) that have
+// to follow the columns when the solver reorders them.
+struct ColParam {
+  std::vector<double> host;
+  double* dev = nullptr;
+  hipStream_t s = nullptr;
+  int upload() const {
+    return hipMemcpyAsync(dev, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice, s) == hipSuccess
+               ? 0
+               : fail(LQ_EDEVICE, "column parameters");
+  }
+};
+
 // Mixed-precision CG with reliable updates on a Hermitian positive-definite A.
 // x, b: FP64.  Columns stop when the FP64 residual of A meets tol[c] |b_c|.
+// Converged columns are moved behind the active ones (columns of every
+// vector, the solver state and `cp` are exchanged together), so the operator
+// and the vector kernels only run over the columns still iterating; x and b
+// are put back in their original order before returning.  A_hi and A_lo
+// receive views of the active columns.
 int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int plo, Vec& x, Vec& b,
-             const std::vector<double>& tol, int maxiter, double delta, Counters& cnt) {
+             const std::vector<double>& tol_in, int maxiter, double delta, Counters& cnt, ColParam* cp = nullptr) {
   const int n = b.ncol, nc = b.nc, npar = b.npar, par0 = b.par0;
   hipStream_t s = bl.s;
   Vec r = make_vec(g, 64, nc, n, npar, par0, s);
@@ -71,16 +89,46 @@ int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int pl
   State st(n, s);
   if (!r.ok() || !q64.ok() || !rs.ok() || !p.ok() || !q.ok() || !xs.ok() || !st.ok())
     return fail(LQ_ENOMEM, "cg buffers");
-  std::vector<double> bb;
+  std::vector<double> bb, tol(tol_in);
   int e = col_norms(bl, b, bb);
   if (e) return e;
-  // r = b - A x (FP64)
+  int na = n;  // active columns occupy slots [0, na)
+  // r = b - A x (FP64) on the active columns
   auto true_res = [&]() -> int {
-    int rr = A_hi(q64, x);
+    Vec qv = view(q64, 0, na), xv = view(x, 0, na), bv = view(b, 0, na);
+    int rr = A_hi(qv, xv);
     if (rr) return rr;
-    if ((rr = bl.op(OP_XMY_NORM, &b, &q64))) return rr;
+    if ((rr = bl.op(OP_XMY_NORM, &bv, &qv))) return rr;
     std::swap(r, q64);
-    if (launch_scalar(SC_SET_RR, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if (launch_scalar(SC_SET_RR, bl.partial, bl.gridx, na, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    return 0;
+  };
+  std::vector<double> maxrr(n);
+  std::vector<std::pair<int, int>> swaps;  // applied to x and b, undone at the end
+  // exchange slots a and b of every per-column object (host state must be current)
+  auto swap_slots = [&](int a, int c) -> int {
+    if (a == c) return 0;
+    int rr = 0;
+    for (Vec* v : {&x, &b, &r, &rs, &p, &xs})
+      if ((rr = vec_swap_cols(*v, a, c))) return rr;
+    for (int k = 0; k < ST_STRIDE; ++k) std::swap(st.h(a, k), st.h(c, k));
+    std::swap(bb[a], bb[c]);
+    std::swap(tol[a], tol[c]);
+    std::swap(maxrr[a], maxrr[c]);
+    if (cp) std::swap(cp->host[a], cp->host[c]);
+    swaps.emplace_back(a, c);
+    return 0;
+  };
+  // move the inactive columns behind the active ones; returns the new na
+  auto compact = [&]() -> int {
+    int rr = 0;
+    for (int c = na - 1; c >= 0; --c) {
+      if (st.h(c, ST_ACTIVE) != 0.0) continue;
+      if ((rr = swap_slots(c, na - 1))) return rr;
+      --na;
+    }
+    if ((rr = st.push())) return rr;
+    if (cp && (rr = cp->upload())) return rr;
     return 0;
   };
   for (int c = 0; c < n; ++c) {
@@ -91,74 +139,95 @@ int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int pl
   if ((e = true_res())) return e;
   if ((e = vec_copy(rs, r)) || (e = vec_copy(p, r)) || (e = vec_zero(xs))) return e ? e : fail(LQ_EDEVICE, "copy");
   if ((e = st.pull())) return e;
-  std::vector<double> maxrr(n);
-  int nactive = 0;
   for (int c = 0; c < n; ++c) {
     maxrr[c] = st.h(c, ST_RR);
     const bool act = st.h(c, ST_RR) > tol[c] * tol[c] * bb[c] && bb[c] > 0;
     st.h(c, ST_ACTIVE) = act ? 1.0 : 0.0;
-    nactive += act;
   }
-  if ((e = st.push())) return e;
+  if ((e = compact())) return e;
   bool dirty = false;  // xs holds un-folded updates
   int it = 0;
-  for (; it < maxiter && nactive > 0; ++it) {
-    if ((e = A_lo(q, p))) return e;
-    if ((e = bl.op(OP_DOT, &p, &q))) return e;
-    if (launch_scalar(SC_CG_ALPHA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
-    if ((e = bl.op(OP_CG, &p, &q, &xs, &rs, nullptr, st.d(), ST_ALPHA, ST_ALPHA))) return e;
-    if (launch_scalar(SC_CG_BETA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+  for (; it < maxiter && na > 0; ++it) {
+    Vec pv = view(p, 0, na), qv = view(q, 0, na), xsv = view(xs, 0, na), rsv = view(rs, 0, na);
+    if ((e = A_lo(qv, pv))) return e;
+    if ((e = bl.op(OP_DOT, &pv, &qv))) return e;
+    if (launch_scalar(SC_CG_ALPHA, bl.partial, bl.gridx, na, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if ((e = bl.op(OP_CG, &pv, &qv, &xsv, &rsv, nullptr, st.d(), ST_ALPHA, ST_ALPHA))) return e;
+    if (launch_scalar(SC_CG_BETA, bl.partial, bl.gridx, na, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
     if (cnt.fault == 1 && it == 0) {
       // injected NaN in the first reduction (host-forced test of the numeric guard)
-      if ((e = st.pull())) return e;
+      if ((e = st.pull(na))) return e;
       st.h(0, ST_FLAG) = 2.0;
-      if ((e = st.push())) return e;
+      if ((e = st.push(na))) return e;
     }
     dirty = true;
-    if ((e = st.pull())) return e;
-    bool update = false;
-    for (int c = 0; c < n; ++c) {
-      if (st.h(c, ST_ACTIVE) == 0.0) continue;
+    if ((e = st.pull(na))) return e;
+    UpdateRule rule;
+    std::vector<int> restart;  // columns that took no step (alpha = 0): p = r next
+    for (int c = 0; c < na; ++c) {
       if (st.h(c, ST_FLAG) == 2.0) return fail(LQ_ENUMERIC, "NaN/Inf in a CG reduction");
+      if (st.h(c, ST_FLAG) == 1.0) {
+        if (++cnt.restarts > 50 * n) return fail(LQ_EBREAKDOWN, "CG keeps losing positivity of <p, A p>");
+        restart.push_back(c);
+      }
       const double rr = st.h(c, ST_RR);
       maxrr[c] = std::max(maxrr[c], rr);
-      if (rr < delta * delta * maxrr[c] || rr < tol[c] * tol[c] * bb[c]) update = true;
+      rule.column(rr, maxrr[c], tol[c] * tol[c] * bb[c], delta);
     }
+    const bool update = rule.fire();
+    for (int c : restart) {
+      st.h(c, ST_FLAG) = 0.0;
+      st.h(c, ST_BETA) = 0.0;
+    }
+    if (!restart.empty() && (e = st.push(na))) return e;
     if (update || it == maxiter - 1) {
       ++cnt.reliable;
-      if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, n, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
-      if ((e = vec_zero(xs))) return e;
+      if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, na, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
+      if ((e = vec_zero(xsv))) return e;
       dirty = false;
       // keep the CG direction scalars (beta) computed in sloppy precision
       if ((e = true_res())) return e;
-      if ((e = vec_copy(rs, r))) return e;
-      if ((e = st.pull())) return e;
-      nactive = 0;
-      for (int c = 0; c < n; ++c) {
+      {
+        Vec rv = view(r, 0, na);
+        if ((e = vec_copy(rsv, rv))) return e;
+      }
+      if ((e = st.pull(na))) return e;
+      for (int c = 0; c < na; ++c) {
         const double rr = st.h(c, ST_RR);
         if (!std::isfinite(rr)) return fail(LQ_ENUMERIC, "NaN/Inf in the true residual");
         maxrr[c] = rr;
-        if (st.h(c, ST_ACTIVE) != 0.0 && rr <= tol[c] * tol[c] * bb[c]) {
+        if (rr <= tol[c] * tol[c] * bb[c]) {
           st.h(c, ST_ACTIVE) = 0.0;
           st.h(c, ST_BETA) = 0.0;
         }
-        nactive += st.h(c, ST_ACTIVE) != 0.0;
       }
-      if ((e = st.push())) return e;
+      if ((e = compact())) return e;
     }
-    if ((e = bl.op(OP_XPAY, &rs, &p, nullptr, nullptr, nullptr, st.d(), ST_BETA, ST_BETA))) return e;
+    if (na == 0) {
+      ++it;
+      break;
+    }
+    Vec rsn = view(rs, 0, na), pn = view(p, 0, na);
+    if ((e = bl.op(OP_XPAY, &rsn, &pn, nullptr, nullptr, nullptr, st.d(), ST_BETA, ST_BETA))) return e;
   }
-  if (dirty) {
-    if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, n, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
+  if (dirty && na > 0) {
+    if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, na, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
   }
+  const int left = na;
+  // original column order of x and b (and of the caller's column parameters)
+  for (auto it2 = swaps.rbegin(); it2 != swaps.rend(); ++it2) {
+    if ((e = vec_swap_cols(x, it2->first, it2->second)) || (e = vec_swap_cols(b, it2->first, it2->second))) return e;
+    if (cp) std::swap(cp->host[it2->first], cp->host[it2->second]);
+  }
+  if (cp && !swaps.empty() && (e = cp->upload())) return e;
   cnt.iters += it;
-  return nactive > 0 ? LQ_ENOCONV : LQ_OK;
+  return left > 0 ? LQ_ENOCONV : LQ_OK;
 }
 
 // Mixed-precision BiCGStab with reliable updates for a non-Hermitian M.
-// M_fused (optional): the sloppy operator with fused reductions (mode 1:
-// <rh, out>, mode 2: <out, in> and |out|^2) as partials over 64-site tiles.
-using FusedFn = std::function<int(Vec& out, const Vec& in, int mode, double* red, const Vec* rh)>;
+// M_fused (optional): the sloppy operator with the fused reductions <out, in>
+// and |out|^2 (mode 2) as partials over 64-site tiles.
+using FusedFn = std::function<int(Vec& out, const Vec& in, int mode, double* red)>;
 
 int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int plo, Vec& x, Vec& b,
                    const std::vector<double>& tol, int maxiter, double delta, Counters& cnt,
@@ -218,20 +287,16 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
   bool dirty = false;
   int it = 0;
   for (; it < maxiter && nactive > 0; ++it) {
-    if (M_fused) {
-      // <rhat, v> computed by the stencil that produces v
-      if ((e = (*M_fused)(v, p, 1, redbuf.as<double>(), &rhat))) return e;
-      if (launch_scalar(SC_BICG_ALPHA, redbuf.as<double>(), fused_tiles, n, st.d(), s))
-        return fail(LQ_EDEVICE, "scalar");
-    } else {
-      if ((e = M_lo(v, p))) return e;
-      if ((e = bl.op(OP_DOT, &rhat, &v))) return e;
-      if (launch_scalar(SC_BICG_ALPHA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
-    }
+    // <rhat, v> by a separate pass: fused into the stencil (mode 1) it measured
+    // slower than the pass, since the extra rhat stream raises the register
+    // pressure of the already heaviest epilogue
+    if ((e = M_lo(v, p))) return e;
+    if ((e = bl.op(OP_DOT, &rhat, &v))) return e;
+    if (launch_scalar(SC_BICG_ALPHA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
     if ((e = bl.op(OP_AXMY, &v, &rs, nullptr, nullptr, nullptr, st.d(), ST_ALPHA, ST_ALPHA))) return e;
     if (M_fused) {
       // <t, s> and |t|^2 computed by the stencil that produces t = M s
-      if ((e = (*M_fused)(t, rs, 2, redbuf.as<double>(), nullptr))) return e;
+      if ((e = (*M_fused)(t, rs, 2, redbuf.as<double>()))) return e;
       if (launch_scalar(SC_BICG_OMEGA, redbuf.as<double>(), fused_tiles, n, st.d(), s))
         return fail(LQ_EDEVICE, "scalar");
     } else {
@@ -243,7 +308,8 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
     if (launch_scalar(SC_BICG_BETA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
     dirty = true;
     if ((e = st.pull())) return e;
-    bool update = false, breakdown = false;
+    bool breakdown = false;
+    UpdateRule rule;
     for (int c = 0; c < n; ++c) {
       if (st.h(c, ST_ACTIVE) == 0.0) continue;
       if (st.h(c, ST_FLAG) == 2.0) return fail(LQ_ENUMERIC, "NaN/Inf in a BiCGStab reduction");
@@ -251,8 +317,9 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
       const double rr = st.h(c, ST_RR);
       if (!std::isfinite(rr)) return fail(LQ_ENUMERIC, "NaN/Inf residual");
       maxrr[c] = std::max(maxrr[c], rr);
-      if (rr < delta * delta * maxrr[c] || rr < tol[c] * tol[c] * bb[c]) update = true;
+      rule.column(rr, maxrr[c], tol[c] * tol[c] * bb[c], delta);
     }
+    const bool update = rule.fire();
     if (update || breakdown || it == maxiter - 1) {
       ++cnt.reliable;
       if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, n, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
@@ -352,8 +419,8 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
       if ((e = blas_prepare(c, ble, g, 1, n_rhs, s))) return e;
       OpFn M64 = [&](Vec& o, const Vec& i) { return tm_schur(env, 64, o, i, to64); };
       OpFn Mlo = [&](Vec& o, const Vec& i) { return tm_schur(env, plo, o, i, tolo); };
-      FusedFn Mfused = [&](Vec& o, const Vec& i, int mode, double* red, const Vec* rh) {
-        return tm_schur(env, plo, o, i, tolo, mode, red, rh);
+      FusedFn Mfused = [&](Vec& o, const Vec& i, int mode, double* red) {
+        return tm_schur(env, plo, o, i, tolo, mode, red);
       };
       const bool fuse = getenv("LQ_NO_FUSED_REDUCTIONS") == nullptr;
       std::vector<double> tol_s(n_rhs, 0.5 * tol);
@@ -380,14 +447,17 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
       Vec bn = make_vec(g, 64, 12, n_rhs, 2, 0, s);
       if (!tmp64.ok() || !tmplo.ok() || !bn.ok()) return fail(LQ_ENOMEM, "cgne buffers");
       if ((e = Ddag64(bn, b))) return e;
+      // the solver passes views of its active columns: temporaries of the same width
       OpFn N64 = [&](Vec& o, const Vec& i) {
-        int r = D64(tmp64, i);
-        return r ? r : Ddag64(o, tmp64);
+        Vec t = view(tmp64, 0, i.ncol);
+        int r = D64(t, i);
+        return r ? r : Ddag64(o, t);
       };
       OpFn Nlo = [&](Vec& o, const Vec& i) {
-        int r = kind == LQ_OVERLAP ? overlap_D(env, plo, tmplo, i, false) : wilson_D(env, plo, tmplo, i, false);
+        Vec t = view(tmplo, 0, i.ncol);
+        int r = kind == LQ_OVERLAP ? overlap_D(env, plo, t, i, false) : wilson_D(env, plo, t, i, false);
         if (r) return r;
-        return kind == LQ_OVERLAP ? overlap_D(env, plo, o, tmplo, true) : wilson_D(env, plo, o, tmplo, true);
+        return kind == LQ_OVERLAP ? overlap_D(env, plo, o, t, true) : wilson_D(env, plo, o, t, true);
       };
       std::vector<double> tol_n(n_rhs, 0.1 * tol);
       for (int pass = 0; pass < 6; ++pass) {
@@ -510,10 +580,17 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
     Vec to64 = make_vec(g, 64, 3, ncol, 1, 1, s);
     Vec tolo = make_vec(g, plo, 3, ncol, 1, 1, s);
     if (!to64.ok() || !tolo.ok()) return fail(LQ_ENOMEM, "HISQ buffers");
-    OpFn A64 = [&](Vec& o, const Vec& i) { return stag_normal_even(env, 64, o, i, to64, dm2.as<double>(), 0.0); };
-    OpFn Alo = [&](Vec& o, const Vec& i) { return stag_normal_even(env, plo, o, i, tolo, dm2.as<double>(), 0.0); };
+    OpFn A64 = [&](Vec& o, const Vec& i) {
+      Vec t = view(to64, 0, i.ncol);
+      return stag_normal_even(env, 64, o, i, t, dm2.as<double>(), 0.0);
+    };
+    OpFn Alo = [&](Vec& o, const Vec& i) {
+      Vec t = view(tolo, 0, i.ncol);
+      return stag_normal_even(env, plo, o, i, t, dm2.as<double>(), 0.0);
+    };
     std::vector<double> tolv(ncol, tol);
-    const int rs = cg_mixed(ble, g, A64, Alo, plo, y, brep, tolv, maxiter, delta, cnt);
+    ColParam cpm{m2col, dm2.as<double>(), s};  // m^2 per column follows the solver's reordering
+    const int rs = cg_mixed(ble, g, A64, Alo, plo, y, brep, tolv, maxiter, delta, cnt, &cpm);
     if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
     status = rs;
     std::vector<double> res;

@@ -83,12 +83,12 @@ __global__ void __launch_bounds__(kStencilMaxThreads) stag_kernel(StagArgs A) {
     for (int a = 0; a < 3; ++a) out[a] = kf * af[r][a] + kl * al[r][a];
     if constexpr (EPI == SEPI_XPAY) {
       cx<R> x[3];
-      IO<P, 3>::load(A.x, blk_index(A.x, col, par), cb, x);
+      IO<P, 3>::template load<true>(A.x, blk_index(A.x, col, par), cb, x);
       const R a = A.acol ? (R)A.acol[col] : (R)A.a;
 #pragma unroll
       for (int i = 0; i < 3; ++i) out[i] = a * x[i] + out[i];
     }
-    IO<P, 3>::store(A.out, blk_index(A.out, col, par), cb, out);
+    IO<P, 3>::template store<true>(A.out, blk_index(A.out, col, par), cb, out);
   }
 }
 

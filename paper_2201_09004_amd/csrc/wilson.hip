@@ -12,7 +12,7 @@ extern template int launch_wilson_prec<16>(const WilsonArgs& A, int nr, int bs, 
 
 int launch_wilson(const WilsonArgs& A, hipStream_t s) {
   if (A.prec == 16 && (A.epi == EPI_CLOVINV || A.epi == EPI_XMY_CLOVINV || A.epi == EPI_SITE ||
-                       A.epi == EPI_XMY_RDOT || A.epi == EPI_XMY_RTS))
+                       A.epi == EPI_XMY_RTS))
     return -1;
   const int nr = A.nr > 0 ? A.nr : 1;
   // slab depth must divide Lz (0 = lexicographic traversal)

@@ -137,7 +137,7 @@ __device__ __forceinline__ void apply_full6(const void* base, int Vh, int par, i
     cx<R> s = {0, 0};
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      T2 d = p[tix(g, i * 6 + j, 36, cb, Vh)];
+      T2 d = ldx<true>(p + tix(g, i * 6 + j, 36, cb, Vh));
       fma(s, cx<R>{(R)d.x, (R)d.y}, v[j]);
     }
     y[i] = s;
@@ -158,7 +158,7 @@ __device__ __forceinline__ void apply_full6_nr(const void* base, int Vh, int par
     for (int r = 0; r < NR; ++r) y[r][i] = {0, 0};
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      T2 d = p[tix(g, i * 6 + j, 36, cb, Vh)];
+      T2 d = ldx<true>(p + tix(g, i * 6 + j, 36, cb, Vh));
       const cx<R> m = {(R)d.x, (R)d.y};
 #pragma unroll
       for (int r = 0; r < NR; ++r)
@@ -181,7 +181,7 @@ __device__ __forceinline__ void apply_herm6(const void* base, int Vh, int par, i
   R d[6];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    T2 e = p[tix(g, k, 18, cb, Vh)];
+    T2 e = ldx<true>(p + tix(g, k, 18, cb, Vh));
     d[2 * k] = (R)e.x;
     d[2 * k + 1] = (R)e.y;
   }
@@ -192,7 +192,7 @@ __device__ __forceinline__ void apply_herm6(const void* base, int Vh, int par, i
   for (int i = 1; i < 6; ++i) {
 #pragma unroll
     for (int j = 0; j < i; ++j) {
-      T2 e = p[tix(g, k, 18, cb, Vh)];
+      T2 e = ldx<true>(p + tix(g, k, 18, cb, Vh));
       ++k;
       cx<R> l = {(R)e.x, (R)e.y};
       fma(y[i], l, v[j]);
@@ -201,19 +201,24 @@ __device__ __forceinline__ void apply_herm6(const void* base, int Vh, int par, i
   }
 }
 
-template <int P, int NE, bool DAG, int EPI, int NR>
-#ifndef LQ_STENCIL_ATTR
-#define LQ_STENCIL_ATTR __launch_bounds__(kStencilMaxThreads)
+// Minimum waves per SIMD asked of the compiler for the FP64 variants (their
+// accumulators and operands are twice as wide; 1 leaves the register budget
+// at 256 and occupancy at 2 waves).
+#ifndef LQ_MINW64
+#define LQ_MINW64 1
 #endif
-__global__ void LQ_STENCIL_ATTR wilson_kernel(WilsonArgs A) {
+template <int P, int NE, bool DAG, int EPI, int NR>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, kStencilMaxThreads),
+                               amdgpu_waves_per_eu(P == 64 ? LQ_MINW64 : 1)))
+wilson_kernel(WilsonArgs A) {
   using R = typename RealOf<P>::T;
-  constexpr bool XMY = EPI == EPI_XMY_CLOVINV || EPI == EPI_XMY_RDOT || EPI == EPI_XMY_RTS;
-  constexpr int RED = EPI == EPI_XMY_RDOT ? 1 : EPI == EPI_XMY_RTS ? 2 : 0;
+  constexpr bool XMY = EPI == EPI_XMY_CLOVINV || EPI == EPI_XMY_RTS;
+  constexpr bool RED = EPI == EPI_XMY_RTS;
   const int ngrp = (A.ncol + NR - 1) / NR;
   int par, cb, grp, c[4], tile = 0;
   const int status = stencil_site(A.g, A.par_out, A.slab, ngrp, A.sh, par, cb, grp, c, &tile);
   // lanes past the end of the last tile stay only to join the wave reductions
-  if (status == 0 || (RED == 0 && status != 1)) return;
+  if (status == 0 || (!RED && status != 1)) return;
   const bool live = status == 1;
   const int col0 = grp * NR;
   const int nv = min(NR, A.ncol - col0);  // <= 0 for waves without columns
@@ -251,19 +256,11 @@ __global__ void LQ_STENCIL_ATTR wilson_kernel(WilsonArgs A) {
       for (int i = 0; i < 12; ++i) out[i] = acc[r][i];
     } else if constexpr (XMY) {
       cx<R> x[12];
-      IO<P, 12>::load(A.x, blk_index(A.x, col, par), cb, x);
+      IO<P, 12>::template load<true>(A.x, blk_index(A.x, col, par), cb, x);
 #pragma unroll
       for (int i = 0; i < 12; ++i) out[i] = x[i] - acc[r][i];
       if (live) {
-        if constexpr (RED == 1) {
-          cx<R> h[12];
-          IO<P, 12>::load(A.rh, blk_index(A.rh, col, par), cb, h);
-#pragma unroll
-          for (int i = 0; i < 12; ++i) {
-            red[r][0] += (double)h[i].re * (double)out[i].re + (double)h[i].im * (double)out[i].im;
-            red[r][1] += (double)h[i].re * (double)out[i].im - (double)h[i].im * (double)out[i].re;
-          }
-        } else if constexpr (RED == 2) {
+        if constexpr (RED) {
 #pragma unroll
           for (int i = 0; i < 12; ++i) {
             red[r][0] += (double)out[i].re * (double)x[i].re + (double)out[i].im * (double)x[i].im;
@@ -274,7 +271,7 @@ __global__ void LQ_STENCIL_ATTR wilson_kernel(WilsonArgs A) {
       }
     } else if constexpr (EPI == EPI_XPAY || EPI == EPI_XPAY_G5 || EPI == EPI_CHEB) {
       cx<R> x[12];
-      IO<P, 12>::load(A.x, blk_index(A.x, col, par), cb, x);
+      IO<P, 12>::template load<true>(A.x, blk_index(A.x, col, par), cb, x);
       const R a = A.acol ? (R)A.acol[col] : (R)A.a;
 #pragma unroll
       for (int i = 0; i < 12; ++i) out[i] = a * x[i] + acc[r][i];
@@ -285,19 +282,19 @@ __global__ void LQ_STENCIL_ATTR wilson_kernel(WilsonArgs A) {
       if constexpr (EPI == EPI_CHEB) {
         cx<R> v[12];
         const R s1 = (R)A.s1, ck = (R)A.ck, s2 = (R)A.s2;
-        IO<P, 12>::load(A.v, blk_index(A.v, col, par), cb, v);
+        IO<P, 12>::template load<true>(A.v, blk_index(A.v, col, par), cb, v);
 #pragma unroll
         for (int i = 0; i < 12; ++i) out[i] = s1 * out[i] + ck * v[i];
-        IO<P, 12>::load(A.b1, blk_index(A.b1, col, par), cb, v);
+        IO<P, 12>::template load<true>(A.b1, blk_index(A.b1, col, par), cb, v);
 #pragma unroll
         for (int i = 0; i < 12; ++i) out[i] = out[i] + s2 * v[i];
-        IO<P, 12>::load(A.b2, blk_index(A.b2, col, par), cb, v);
+        IO<P, 12>::template load<true>(A.b2, blk_index(A.b2, col, par), cb, v);
 #pragma unroll
         for (int i = 0; i < 12; ++i) out[i] = out[i] - v[i];
       }
     } else if constexpr (EPI == EPI_SITE) {
       cx<R> x[12];
-      IO<P, 12>::load(A.x, blk_index(A.x, col, par), cb, x);
+      IO<P, 12>::template load<true>(A.x, blk_index(A.x, col, par), cb, x);
       apply_herm6<P>(A.clov, A.g.Vh, par, 0, cb, x, out);
       apply_herm6<P>(A.clov, A.g.Vh, par, 1, cb, x + 6, out + 6);
       const R mu = (R)A.mu_tw;
@@ -306,9 +303,9 @@ __global__ void LQ_STENCIL_ATTR wilson_kernel(WilsonArgs A) {
 #pragma unroll
       for (int i = 6; i < 12; ++i) out[i] = out[i] - mu * times_i(x[i]) + acc[r][i];
     }
-    if (live) IO<P, 12>::store(A.out, blk_index(A.out, col, par), cb, out);
+    if (live) IO<P, 12>::template store<true>(A.out, blk_index(A.out, col, par), cb, out);
   }
-  if constexpr (RED != 0) {
+  if constexpr (RED) {
     // wave butterfly (fixed order) and one partial per (column, 64-site tile)
     const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
     const int ntile = (nsite + 63) >> 6;
@@ -342,7 +339,7 @@ inline void launch_one(const WilsonArgs& A, int bs, hipStream_t s) {
 // epilogues with register-blocked variants (NR > 1)
 constexpr bool epi_blocked(int epi) {
   return epi == EPI_CLOVINV || epi == EPI_XMY_CLOVINV || epi == EPI_XPAY || epi == EPI_XPAY_G5 || epi == EPI_CHEB ||
-         epi == EPI_XMY_RDOT || epi == EPI_XMY_RTS;
+         epi == EPI_XMY_RTS;
 }
 
 template <int P, int NE, int EPI>
@@ -385,7 +382,6 @@ inline int launch_epi(const WilsonArgs& A, int nr, int bs, hipStream_t s) {
     switch (A.epi) {
       case EPI_CLOVINV: return launch_nr<P, NE, EPI_CLOVINV>(A, nr, bs, s);
       case EPI_XMY_CLOVINV: return launch_nr<P, NE, EPI_XMY_CLOVINV>(A, nr, bs, s);
-      case EPI_XMY_RDOT: return launch_nr<P, NE, EPI_XMY_RDOT>(A, nr, bs, s);
       case EPI_XMY_RTS: return launch_nr<P, NE, EPI_XMY_RTS>(A, nr, bs, s);
       case EPI_SITE: return launch_nr<P, NE, EPI_SITE>(A, 1, bs, s);
       default: break;

@@ -351,3 +351,22 @@ def test_hisq_column_blocking_bitwise_identical(ctx, prec, monkeypatch):
         assert rel(outs[0], want) < 2 * TOL[prec]
     finally:
         L.lq_field_free(f)
+
+
+def test_fp16_subnormal_sites_are_flushed(ctx):
+    """A site whose largest component is below the smallest normal FP32 number
+    is stored as zero in FP16 (its reciprocal norm would overflow); the rest
+    of the field keeps the FP16 tolerance and nothing becomes NaN."""
+    Lx = (4, 4, 4, 8)
+    U, f = _wilson_setup(ctx, Lx, 31)
+    psi = synth.gaussian_spinor(Lx, 1, 32)
+    psi[0, 0, 0, 0, :3] *= 1e-40   # FP32-subnormal sites
+    psi[0, 1, 2, 3, 1] *= 1e-41
+    m = 0.1
+    try:
+        out = L.lq_apply(ctx, L.action(L.LQ_WILSON, m=m), f, L.LQ_OP_D, 16, psi)
+        assert np.isfinite(out).all()
+        want = W.wilson(U, psi[0], m)[None]
+        assert rel(out, want) < TOL[16]
+    finally:
+        L.lq_field_free(f)
