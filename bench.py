@@ -17,6 +17,7 @@ Other workloads (--workload):
            (sec. 2.3, Fig. 2); one step = one eps application
   serve    the serving loop: Poisson arrivals of 12-column twisted-clover and
            HISQ requests on 16^3x32, 24^3x64 and 32^3x64, p50/p99 latency
+  wilson   plain Wilson CG on the normal equations, FP64, 8^4, kappa = 0.12
 
 Printed: one JSON line with the workload's throughput, the roofline of its
 dominant stencil kernel (HIP-event average duration on the kernel's stream and
@@ -373,6 +374,64 @@ def bench_hisq(args, L, torch):
     }
 
 
+def bench_wilson(args, L, torch):
+    """Plain Wilson CG on the normal equations, FP64, 8^4, kappa = 0.12 (m = 1/6),
+    links exp(i 0.3 H) seed 1001, one Gaussian source: a cache-resident latency
+    configuration (working set 3.9 MB)."""
+    import numpy as np
+
+    import synth
+
+    Lw = (8, 8, 8, 8)
+    m = 1.0 / (2 * 0.12) - 4.0
+    dev = torch.device("cuda:0")
+    U = synth.su3_field(Lw, 0.3, SEED)
+    b = synth.gaussian_spinor(Lw, 1, 2001)
+    ctx = L.lq_init(0)
+    field = L.lq_gauge_load(ctx, Lw, torch.from_numpy(U).to(dev))
+    act = L.action(L.LQ_WILSON, m=m)
+    prm = L.params(tol=1e-10, sloppy_bits=64)
+    b_d = torch.from_numpy(b).to(dev)
+    for _ in range(args.warmup):
+        L.lq_solve(ctx, act, field, prm, b_d)
+    torch.cuda.synchronize()
+    L.lq_profile(ctx, True)
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x, st = L.lq_solve(ctx, act, field, prm, b_d)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernels = profile_table(L, ctx, ["wilson64_xpay", "blas"])
+    L.lq_profile(ctx, False)
+    cpu = None
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import solve as OS
+        from oracle import wilson as W
+        with threadpool_limits(1):
+            ta = time.perf_counter()
+            xo, it = OS.cgne(lambda v: W.wilson(U, v, m), lambda v: W.gamma5(W.wilson(U, W.gamma5(v), m)), b[0],
+                             tol=1e-10)
+            tb = time.perf_counter()
+        cpu = {"value": 1.0 / (tb - ta), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"FP64 numpy oracle CGNE, 1 thread, the same 8^4 solve ({tb - ta:.1f} s, {it} iterations)"}
+    L.lq_field_free(field)
+    L.lq_finalize(ctx)
+    value = args.steps / (t1 - t0)
+    return {
+        "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round((t1 - t0) / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "wilson_cgne_fp64_8x8x8x8_1rhs", "lattice": list(Lw), "kappa": 0.12, "m": m,
+                   "links": "exp(i*0.3*H) seed 1001", "tol": 1e-10},
+        "roofline": None, "cpu_baseline": cpu, "iters": [s["iters"] for s in stats],
+        "worst_true_rel_res": max(s["true_rel_res"] for s in stats), "kernels": kernels,
+    }
+
+
 def bench_overlap(args, L, torch):
     import numpy as np
 
@@ -521,7 +580,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("tm", "hisq", "overlap", "serve"), default="tm")
+    ap.add_argument("--workload", choices=("tm", "hisq", "overlap", "serve", "wilson"), default="tm")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 single-column comparison")
     ap.add_argument("--recon12", type=int, default=0)
@@ -537,7 +596,8 @@ def main():
     from paper_2201_09004_amd import lq as L
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    fn = {"tm": bench_tm, "hisq": bench_hisq, "overlap": bench_overlap, "serve": bench_serve}[args.workload]
+    fn = {"tm": bench_tm, "hisq": bench_hisq, "overlap": bench_overlap, "serve": bench_serve,
+          "wilson": bench_wilson}[args.workload]
     out = fn(args, L, torch)
     print(json.dumps(out), flush=True)
 

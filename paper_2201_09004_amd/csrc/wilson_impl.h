@@ -201,15 +201,18 @@ __device__ __forceinline__ void apply_herm6(const void* base, int Vh, int par, i
   }
 }
 
-// Minimum waves per SIMD asked of the compiler for the FP64 variants (their
-// accumulators and operands are twice as wide; 1 leaves the register budget
+// Minimum waves per SIMD asked of the compiler for the FP64 / FP32 variants (the
+// register-blocked ones use up to 256 VGPRs; 1 leaves the register budget
 // at 256 and occupancy at 2 waves).
 #ifndef LQ_MINW64
 #define LQ_MINW64 1
 #endif
+#ifndef LQ_MINW32
+#define LQ_MINW32 1
+#endif
 template <int P, int NE, bool DAG, int EPI, int NR>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, kStencilMaxThreads),
-                               amdgpu_waves_per_eu(P == 64 ? LQ_MINW64 : 1)))
+                               amdgpu_waves_per_eu(P == 64 ? LQ_MINW64 : P == 32 ? LQ_MINW32 : 1)))
 wilson_kernel(WilsonArgs A) {
   using R = typename RealOf<P>::T;
   constexpr bool XMY = EPI == EPI_XMY_CLOVINV || EPI == EPI_XMY_RTS;

@@ -129,3 +129,25 @@ def test_hisq_normal_fp16_12col():
     finally:
         L.lq_field_free(fh)
         L.lq_finalize(ctx)
+
+
+def test_overlap_sign_properties_fp32(env):
+    """The order-200 sign function at full size: eps(H)^2 = 1 and eps(H)
+    Hermitian, to the polynomial error plus FP32 rounding (properties that
+    hold at any size; the sign function has no per-site evaluation)."""
+    import torch
+    ctx, f, U = env
+    lo, hi = L.lq_hw_bounds(ctx, L.action(L.LQ_OVERLAP, m=0.015, rho=1.5), f, 200)
+    a, b = 0.9 * lo * lo, 1.1 * hi * hi
+    act = L.action(L.LQ_OVERLAP, m=0.015, rho=1.5, cheb_N=200, cheb_a=a, cheb_b=b)
+    v = torch.from_numpy(synth.gaussian_spinor(LAT, 2, 2005)).cuda()
+    y = L.lq_apply(ctx, act, f, L.LQ_OP_SIGN, 32, v)
+    z = L.lq_apply(ctx, act, f, L.LQ_OP_SIGN, 32, y)
+    torch.cuda.synchronize()
+    sq = float(torch.linalg.vector_norm(z - v) / torch.linalg.vector_norm(v))
+    d01 = complex(torch.vdot(v[0].flatten(), y[1].flatten()))
+    d10 = complex(torch.vdot(y[0].flatten(), v[1].flatten()))
+    herm = abs(d01 - d10) / (float(torch.linalg.vector_norm(v[0])) * float(torch.linalg.vector_norm(v[1])))
+    log("eps^2 - 1:", sq, "hermiticity:", herm, "interval", a, b)
+    assert sq < 1e-4
+    assert herm < 1e-5
