@@ -208,15 +208,23 @@ int launch_blas(const BlasArgs& A, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ scalars
-// The scalar kernels run one wave (64 lanes) per column; every lane executes
-// the same code and holds the same values.  The partials of a column are
-// summed lane-strided in a fixed order, then by a butterfly whose result is
-// bitwise identical in every lane (fixed order, independent of the batch).
+// The scalar kernels run one workgroup of kScalarThreads per column; every
+// thread executes the same code and ends with the same values.  The partials
+// of a column are summed thread-strided in a fixed order, then by a wave
+// butterfly and a fixed-order sum over the waves, so the result is bitwise
+// identical in every thread and independent of timing and of the batch.
+constexpr int kScalarThreads = 256;
 __device__ __forceinline__ double sum_r(const double* p, int gridx, int k) {
+  __shared__ double wsum[kScalarThreads / 64];
   double s = 0;
-  for (int b = (int)threadIdx.x; b < gridx; b += 64) s += p[b * 4 + k];
+  for (int b = (int)threadIdx.x; b < gridx; b += kScalarThreads) s += p[b * 4 + k];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  return s;
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double t = 0;
+  for (int w = 0; w < kScalarThreads / 64; ++w) t += wsum[w];
+  __syncthreads();  // wsum is reused by the next sum
+  return t;
 }
 __device__ __forceinline__ cx<double> sum_c(const double* p, int gridx, int k) {
   return {sum_r(p, gridx, k), sum_r(p, gridx, k + 1)};
@@ -232,6 +240,12 @@ __global__ void scalar_kernel(int op, const double* partial, int gridx, int ncol
   if (col >= ncol) return;
   double* s = st + (int64_t)col * ST_STRIDE;
   const double* p = partial + (int64_t)col * gridx * 4;
+  // the three partial sums every operation draws on, by the whole workgroup;
+  // then one wave reads and updates the state (lanes in lockstep, so every
+  // read precedes every write)
+  const double r0 = sum_r(p, gridx, 0), r1 = sum_r(p, gridx, 1), r2 = sum_r(p, gridx, 2);
+  if (threadIdx.x >= 64) return;
+  const cx<double> c01 = {r0, r1};
   const bool active = s[ST_ACTIVE] != 0.0;
   auto setc = [&](int off, cx<double> v) { s[off] = v.re; s[off + 1] = v.im; };
   auto getc = [&](int off) { return cx<double>{s[off], s[off + 1]}; };
@@ -240,7 +254,7 @@ __global__ void scalar_kernel(int op, const double* partial, int gridx, int ncol
       // <p, A p> <= 0 can only come from rounding in low-precision storage
       // (A is positive definite): flag a restart of the column (flag 1) and
       // take no step; a non-finite value is a numeric error (flag 2)
-      const double pap = sum_r(p, gridx, 0);
+      const double pap = r0;
       double a = s[ST_RR] / pap;
       if (!isfinite(pap)) {
         s[ST_FLAG] = 2;
@@ -253,7 +267,7 @@ __global__ void scalar_kernel(int op, const double* partial, int gridx, int ncol
       break;
     }
     case SC_CG_BETA: {
-      const double rr = sum_r(p, gridx, 0);
+      const double rr = r0;
       double b = rr / s[ST_RR];
       if (!isfinite(rr)) s[ST_FLAG] = 2;
       if (!isfinite(b)) b = 0;
@@ -262,23 +276,23 @@ __global__ void scalar_kernel(int op, const double* partial, int gridx, int ncol
       break;
     }
     case SC_BICG_ALPHA: {
-      const cx<double> d = sum_c(p, gridx, 0);
+      const cx<double> d = c01;
       cx<double> a = cdiv(getc(ST_RHO), d);
       if (!finite_c(a) || (d.re == 0 && d.im == 0)) { s[ST_FLAG] = 1; a = {0, 0}; }
       setc(ST_ALPHA, active ? a : cx<double>{0, 0});
       break;
     }
     case SC_BICG_OMEGA: {
-      const cx<double> ts = sum_c(p, gridx, 0);
-      const double tt = sum_r(p, gridx, 2);
+      const cx<double> ts = c01;
+      const double tt = r2;
       cx<double> w = {ts.re / tt, ts.im / tt};
       if (!finite_c(w) || tt == 0.0) { s[ST_FLAG] = 1; w = {0, 0}; }
       setc(ST_OMEGA, active ? w : cx<double>{0, 0});
       break;
     }
     case SC_BICG_BETA: {
-      const cx<double> rho = sum_c(p, gridx, 0);
-      const double rr = sum_r(p, gridx, 2);
+      const cx<double> rho = c01;
+      const double rr = r2;
       cx<double> b = cdiv(rho, getc(ST_RHO)) * cdiv(getc(ST_ALPHA), getc(ST_OMEGA));
       if (!finite_c(b)) { b = {0, 0}; if (active) s[ST_FLAG] = 1; }
       if (!isfinite(rr)) s[ST_FLAG] = 2;
@@ -288,24 +302,24 @@ __global__ void scalar_kernel(int op, const double* partial, int gridx, int ncol
       break;
     }
     case SC_SET_RR:
-      s[ST_RR] = sum_r(p, gridx, 0);
+      s[ST_RR] = r0;
       if (!isfinite(s[ST_RR])) s[ST_FLAG] = 2;
       break;
     case SC_SET_RHO_RR: {
-      const cx<double> d = sum_c(p, gridx, 0);
+      const cx<double> d = c01;
       setc(ST_RHO, conj(d));
-      s[ST_RR] = sum_r(p, gridx, 2);
+      s[ST_RR] = r2;
       break;
     }
     case SC_DOT_TO_AUX:
-      setc(ST_AUX, sum_c(p, gridx, 0));
+      setc(ST_AUX, c01);
       break;
   }
 }
 
 int launch_scalar(int op, const double* partial, int gridx, int ncol, double* st, hipStream_t s) {
   if (ncol == 0) return 0;
-  scalar_kernel<<<ncol, 64, 0, s>>>(op, partial, gridx, ncol, st);
+  scalar_kernel<<<ncol, kScalarThreads, 0, s>>>(op, partial, gridx, ncol, st);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -382,6 +396,7 @@ __global__ void ms_alpha_kernel(MsArgs A, const double* sigma) {
   if (j >= A.nrhs) return;
   double* s = A.st + (int64_t)j * ST_STRIDE;
   const double pap = sum_r(A.partial + (int64_t)j * A.gridx * 4, A.gridx, 0);
+  if (threadIdx.x >= 64) return;  // one wave updates the state (reads before writes)
   double a = s[ST_RR] / pap;
   if (!isfinite(pap)) {
     a = 0;
@@ -416,6 +431,7 @@ __global__ void ms_beta_kernel(MsArgs A) {
   if (j >= A.nrhs) return;
   double* s = A.st + (int64_t)j * ST_STRIDE;
   const double rr = sum_r(A.partial + (int64_t)j * A.gridx * 4, A.gridx, 0);
+  if (threadIdx.x >= 64) return;  // one wave updates the state (reads before writes)
   double b = rr / s[ST_RR];
   if (!isfinite(b)) b = 0.0;
   if (!isfinite(rr)) s[ST_FLAG] = 2;
@@ -444,6 +460,7 @@ __global__ void ms_init_kernel(MsArgs A) {
   if (j >= A.nrhs) return;
   double* s = A.st + (int64_t)j * ST_STRIDE;
   const double rr = sum_r(A.partial + (int64_t)j * A.gridx * 4, A.gridx, 0);
+  if (threadIdx.x >= 64) return;  // one wave updates the state (reads before writes)
   s[ST_RR] = rr;
   s[ST_RR0] = rr;
   s[ST_AUX] = 1.0;
@@ -480,15 +497,15 @@ int launch_ms_p(const MsArgs& A, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 int launch_ms_scalar_alpha(const MsArgs& A, const double* sigma, hipStream_t s) {
-  ms_alpha_kernel<<<A.nrhs, 64, 0, s>>>(A, sigma);
+  ms_alpha_kernel<<<A.nrhs, kScalarThreads, 0, s>>>(A, sigma);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 int launch_ms_scalar_beta(const MsArgs& A, hipStream_t s) {
-  ms_beta_kernel<<<A.nrhs, 64, 0, s>>>(A);
+  ms_beta_kernel<<<A.nrhs, kScalarThreads, 0, s>>>(A);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 int launch_ms_init(const MsArgs& A, hipStream_t s) {
-  ms_init_kernel<<<A.nrhs, 64, 0, s>>>(A);
+  ms_init_kernel<<<A.nrhs, kScalarThreads, 0, s>>>(A);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

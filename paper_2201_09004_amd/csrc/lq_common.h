@@ -382,23 +382,46 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (b % nx) * per + b / nx;
 }
 
+// Site traversal order of the stencil kernels.  The lattice of one parity is
+// cut into blocks of by x bz x bt (y, z, t) planes holding whole x rows; the
+// blocks are walked with y fastest, then z, then t, and each block is walked
+// lexicographically (x, y, z, t) inside.  A block small enough that the sites
+// in flight on one XCD cover most of it keeps the neighbour spinors of all
+// eight directions in that XCD's L2.  The code is the tuned knob:
+//   0         lexicographic (one block: by = Ly, bz = Lz, bt = Lt)
+//   1 .. 255  slabs of that many z planes (by = Ly, bt = Lt)
+//   otherwise by | bz << 8 | bt << 16
+__host__ __device__ inline void traversal_block(const Geom& g, int code, int& by, int& bz, int& bt) {
+  if (code <= 0) {
+    by = g.L[1], bz = g.L[2], bt = g.L[3];
+  } else if (code < 256) {
+    by = g.L[1], bz = code, bt = g.L[3];
+  } else {
+    by = code & 0xff, bz = (code >> 8) & 0xff, bt = (code >> 16) & 0xff;
+  }
+}
+inline bool traversal_valid(const Geom& g, int code) {
+  if (code < 0) return false;
+  int by, bz, bt;
+  traversal_block(g, code, by, bz, bt);
+  return by > 0 && bz > 0 && bt > 0 && g.L[1] % by == 0 && g.L[2] % bz == 0 && g.L[3] % bt == 0;
+}
+inline int traversal_code(int by, int bz, int bt) { return by | (bz << 8) | (bt << 16); }
+
 // Work decomposition of the stencil kernels.  A workgroup owns one tile of 64
 // consecutive sites (in traversal order) and gw = blockDim.x / 64 column
 // groups, one wave per group, so every column group of a site runs on the same
 // CU and the links and site matrices of the tile are fetched from HBM once.
-// Traversal order within a parity: with slab depth bz > 0 the lattice is cut
-// into slabs of bz z-planes, walked slab by slab with t outside z-in-slab, so
-// the t-neighbours of a site come back Lx/2*Ly*bz sites later (within L2)
-// instead of Lx/2*Ly*Lz; bz = 0 is the lexicographic (x, y, z, t) order.
-// Returns false for lanes without work.
+// Sites are taken in the traversal order given by the code (see
+// traversal_block).
 // Launch shape knobs (tuned): sh = gw | tpb << 8 | xcd << 16 with gw column
 // groups and tpb site tiles per workgroup (one wave each), xcd = 1 to apply
 // xcd_remap to the block index.
 // Returns 0 when the whole wave has no sites (it can exit), 1 for a lane with
 // a site, 2 for a lane of the last, partial tile past the end (its site is
 // clamped to the last one so that it can still join wave-wide reductions).
-__device__ __forceinline__ int stencil_site(const Geom& g, int par_out, int bz, int ngrp, int sh, int& par, int& cb,
-                                            int& grp, int c[4], int* tile_out = nullptr) {
+__device__ __forceinline__ int stencil_site(const Geom& g, int par_out, int order, int ngrp, int sh, int& par,
+                                            int& cb, int& grp, int c[4], int* tile_out = nullptr) {
   const int nsite = par_out == 2 ? 2 * g.Vh : g.Vh;
   const int ntile = (nsite + 63) >> 6;
   const int gw = sh & 0xff, tpb = (sh >> 8) & 0xff;
@@ -424,22 +447,28 @@ __device__ __forceinline__ int stencil_site(const Geom& g, int par_out, int bz, 
   if (j >= nsite) j = nsite - 1;
   par = par_out == 2 ? (j >= g.Vh ? 1 : 0) : par_out;
   const int jj = par_out == 2 ? j - par * g.Vh : j;
+  int oy, oz, ot;  // traversal block extents
+  traversal_block(g, order, oy, oz, ot);
   const int xh = jj % g.Lxh;
-  int r = jj / g.Lxh;
-  c[1] = r % g.L[1];
-  r /= g.L[1];
-  // z and t as scalars, stored once: stores to c[2] / c[3] in both branches
+  const int r = jj / g.Lxh;  // x row in traversal order
+  const int rows = oy * oz * ot;
+  const int blk = r / rows;
+  int q = r - blk * rows;
+  const int yi = q % oy;
+  q /= oy;
+  const int zi = q % oz;
+  const int ti = q / oz;
+  const int nby = g.L[1] / oy, nbz = g.L[2] / oz;
+  const int yb = blk % nby, b2 = blk / nby;
+  // coordinates as scalars, each stored once (stores in alternative branches
   // would be merged into one store through a selected pointer, which keeps
-  // the coordinate array in scratch memory
-  const int bzz = bz > 0 ? bz : g.L[2];
-  const int zi = r % bzz;
-  r /= bzz;
-  const int t = bz > 0 ? r % g.L[3] : r;
-  const int z = bz > 0 ? (r / g.L[3]) * bz + zi : zi;
+  // the coordinate array in scratch memory)
+  const int y = yb * oy + yi, z = (b2 % nbz) * oz + zi, t = (b2 / nbz) * ot + ti;
+  c[1] = y;
   c[2] = z;
   c[3] = t;
-  c[0] = 2 * xh + ((c[1] + z + t + par) & 1);
-  cb = xh + g.Lxh * (c[1] + g.L[1] * (z + g.L[2] * t));
+  c[0] = 2 * xh + ((y + z + t + par) & 1);
+  cb = xh + g.Lxh * (y + g.L[1] * (z + g.L[2] * t));
   return status;
 }
 

@@ -21,7 +21,7 @@ struct WilsonArgs {
   int prec, recon, dag, epi;
   int par_out;  // 0, 1, or 2 = both parities
   int ncol;
-  int slab;     // traversal slab depth in z (0: lexicographic), see stencil_site
+  int slab;     // site traversal order code (0: lexicographic), see traversal_block
   int tpb, xcd; // site tiles per workgroup (0: automatic), XCD-aware block order
   int sh;       // packed launch shape, set by the launcher
   int nr;       // columns per thread (register blocking): 1, 2, 3, 4 or 6
@@ -47,7 +47,7 @@ enum { SEPI_HOP = 0, SEPI_XPAY };
 struct StagArgs {
   Geom g;
   int prec, epi, par_out, ncol;
-  int slab;      // traversal slab depth in z (0: lexicographic), see stencil_site
+  int slab;      // site traversal order code (0: lexicographic), see traversal_block
   int tpb, xcd;  // site tiles per workgroup (0: automatic), XCD-aware block order
   int sh;        // packed launch shape, set by the launcher
   int nr;  // columns per thread: 1, 2, 3, 4, 6 or 8

@@ -273,11 +273,29 @@ static void tune_save(lq_ctx* c) {
   fclose(f);
 }
 
-// slab depths worth trying for a lattice: 0 (lexicographic) and divisors of Lz
+// Traversal orders worth trying for a lattice: lexicographic, z slabs of
+// 1-8 planes, and the (y, z, t) blocks of whole x rows with the least surface
+// per site among those of 1.5k-6k sites (about what one XCD has in flight).
 static std::vector<int> slab_candidates(const Geom& g) {
   std::vector<int> v{0};
   for (int bz : {1, 2, 4, 8})
     if (g.L[2] % bz == 0 && bz < g.L[2]) v.push_back(bz);
+  struct Blk {
+    double surf;
+    int code;
+  };
+  std::vector<Blk> blocks;
+  for (int by : {2, 3, 4, 6, 8, 12, 16})
+    for (int bz : {2, 3, 4, 6, 8, 12, 16})
+      for (int bt : {2, 4, 8, 16, 32}) {
+        if (g.L[1] % by || g.L[2] % bz || g.L[3] % bt) continue;
+        if (by == g.L[1] && bt == g.L[3]) continue;  // a z slab, listed above
+        const long sites = (long)g.Lxh * by * bz * bt;
+        if (sites < 1536 || sites > 6144) continue;
+        blocks.push_back({1.0 / by + 1.0 / bz + 1.0 / bt, traversal_code(by, bz, bt)});
+      }
+  std::sort(blocks.begin(), blocks.end(), [](const Blk& a, const Blk& b) { return a.surf < b.surf; });
+  for (size_t k = 0; k < blocks.size() && k < 6; ++k) v.push_back(blocks[k].code);
   return v;
 }
 
@@ -295,11 +313,10 @@ static int tuned(lq_ctx* c, const std::string& key, Args& A, size_t out_bytes, i
   const std::vector<int> slabs = slab_candidates(A.g);
   Shape choice{1, 0, 0, 1};
   if (const char* f = getenv("LQ_TUNE_FORCE")) {
-    // testing hook: force "nr,slab[,tpb,xcd]" wherever the values are candidates
+    // testing hook: force "nr,order[,tpb,xcd]" (nr where it is a candidate, any valid traversal order)
     int nr = 1, bz = 0, tpb = 0, xcd = 1;
     if (sscanf(f, "%d,%d,%d,%d", &nr, &bz, &tpb, &xcd) >= 2) {
-      Shape sh{std::find(nrs.begin(), nrs.end(), nr) != nrs.end() ? nr : 1,
-               std::find(slabs.begin(), slabs.end(), bz) != slabs.end() ? bz : 0,
+      Shape sh{std::find(nrs.begin(), nrs.end(), nr) != nrs.end() ? nr : 1, traversal_valid(A.g, bz) ? bz : 0,
                (tpb == 1 || tpb == 2 || tpb == 4 || tpb == 8) ? tpb : 0, xcd ? 1 : 0};
       apply_shape(A, sh);
       return launch(A, s);
@@ -351,12 +368,16 @@ static int tuned(lq_ctx* c, const std::string& key, Args& A, size_t out_bytes, i
         choice = sh;
       }
     };
-    // coordinate search: columns per thread, then slab depth, then tiles per
-    // workgroup x block order, each around the best shape so far
+    // coordinate search: columns per thread, traversal order, columns per
+    // thread again at that order, then tiles per workgroup x block order, each
+    // around the best shape so far
     for (int nr : nrs) trial(Shape{nr, 0, 0, 1});
     const Shape s0 = choice;
     for (int bz : slabs)
       if (bz != 0) trial(Shape{s0.nr, bz, 0, 1});
+    const Shape sb = choice;
+    for (int nr : nrs)
+      if (nr != sb.nr) trial(Shape{nr, sb.slab, 0, 1});
     const Shape s1 = choice;
     for (int tpb : {0, 1, 2, 4, 8})
       for (int xcd : {1, 0})

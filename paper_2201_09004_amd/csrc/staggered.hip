@@ -117,7 +117,7 @@ static int stag_nr(const StagArgs& A, int nr, int bs, hipStream_t s) {
 
 int launch_stag(const StagArgs& A, hipStream_t s) {
   const int nr = A.nr > 0 ? A.nr : 1;
-  if (A.slab < 0 || (A.slab > 0 && A.g.L[2] % A.slab != 0)) return -1;
+  if (!traversal_valid(A.g, A.slab)) return -1;
   const int bs = 0;
   int r;
   if (A.prec == 64) r = A.epi == SEPI_HOP ? stag_nr<64, SEPI_HOP>(A, nr, bs, s) : stag_nr<64, SEPI_XPAY>(A, nr, bs, s);

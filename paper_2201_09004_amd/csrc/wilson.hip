@@ -15,8 +15,7 @@ int launch_wilson(const WilsonArgs& A, hipStream_t s) {
                        A.epi == EPI_XMY_RTS))
     return -1;
   const int nr = A.nr > 0 ? A.nr : 1;
-  // slab depth must divide Lz (0 = lexicographic traversal)
-  if (A.slab < 0 || (A.slab > 0 && A.g.L[2] % A.slab != 0)) return -1;
+  if (!traversal_valid(A.g, A.slab)) return -1;
   const int bs = 0;
   int r;
   if (A.prec == 64) r = launch_wilson_prec<64>(A, nr, bs, s);

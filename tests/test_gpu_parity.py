@@ -308,7 +308,17 @@ def test_solver_fault_injection(ctx):
 
 
 # ------------------------------------------------------------------ autotuner variants
-FORCES = ["1,0", "2,2", "3,1", "4,0", "6,2", "8,1"]   # "columns per thread, slab depth"
+FORCES = ["1,0", "2,2", "3,1", "4,0", "6,2", "8,1"]   # "columns per thread, traversal order"
+
+
+def _blk(by, bz, bt):
+    """Traversal-order code of (y, z, t) blocks of whole x rows."""
+    return by | (bz << 8) | (bt << 16)
+
+
+# block traversals (and tiles-per-workgroup / block-order knobs) on the two test lattices
+FORCES_W = FORCES + [f"3,{_blk(3, 2, 5)}", f"2,{_blk(2, 4, 2)},2,0"]   # 6x6x4x10
+FORCES_H = FORCES + [f"3,{_blk(2, 3, 5)}", f"4,{_blk(4, 2, 2)},1,1"]   # 6x4x6x10
 
 
 @pytest.mark.parametrize("prec", [64, 32, 16])
@@ -324,7 +334,7 @@ def test_column_blocking_bitwise_identical(ctx, prec, monkeypatch):
         act, op = L.action(L.LQ_TM_CLOVER, m=-0.0695, mu=0.01, c_sw=1.0509), L.LQ_OP_SCHUR
     try:
         outs = []
-        for force in FORCES:
+        for force in FORCES_W:
             monkeypatch.setenv("LQ_TUNE_FORCE", force)
             outs.append(L.lq_apply(ctx, act, f, op, prec, psi))
         for o in outs[1:]:
@@ -342,7 +352,7 @@ def test_hisq_column_blocking_bitwise_identical(ctx, prec, monkeypatch):
     act = L.action(L.LQ_HISQ, m=0.02)
     try:
         outs = []
-        for force in FORCES:
+        for force in FORCES_H:
             monkeypatch.setenv("LQ_TUNE_FORCE", force)
             outs.append(L.lq_apply(ctx, act, f, L.LQ_OP_NORMAL_EVEN, prec, chi))
         for o in outs[1:]:
