@@ -262,12 +262,17 @@ def bench_tm(args, L, torch):
     log("timed", args.steps, "steps:", ms_step, "ms/step; worst residual", worst)
 
     names = [f"wilson{p}_{e}" for p in (32, 64) for e in ("clovinv", "xmy", "xmyt", "xpay", "site")]
-    kernels = profile_table(L, ctx, names + ["blas", "site"])
+    kernels = profile_table(L, ctx, names + [f"{k}_n{n_rhs}" for k in names] + ["blas", "site"])
     L.lq_profile(ctx, False)
-    dom = max((k for k in kernels if k.startswith("wilson32")), key=lambda k: kernels[k]["total_ms"])
+    # dominant kernel by total time; its roofline from the launches at the full
+    # 12-column width (converged columns leave the batch near the end)
+    dom = max((k for k in kernels if k.startswith("wilson32") and "_n" not in k),
+              key=lambda k: kernels[k]["total_ms"])
     Vh = int(np.prod(TM_LAT)) // 2
     alg = wilson_site_bytes(32, dom.split("_")[1], n_rhs, args.recon12) * Vh
-    roof = roofline_for(kernels, dom, alg, measured_traffic(dom, "tm_clover_eo_bicgstab_24x24x24x64_12rhs"))
+    kernels_w = {dom: kernels[f"{dom}_n{n_rhs}"]} if f"{dom}_n{n_rhs}" in kernels else kernels
+    roof = roofline_for(kernels_w, dom, alg, measured_traffic(dom, "tm_clover_eo_bicgstab_24x24x24x64_12rhs"))
+    roof["launches_at_full_width"] = kernels_w[dom]["count"]
     roof["copy_kernel_gbs"] = copy_peak(L, ctx)
 
     fp64 = None
@@ -346,15 +351,15 @@ def bench_hisq(args, L, torch):
     value = n_rhs * args.steps / (t1 - t0)
     worst = max(s["true_rel_res"] for s in stats)
     names = [f"stag{p}_{e}" for p in (16, 32, 64) for e in ("hop", "xpay")]
-    kernels = profile_table(L, ctx, names + ["blas"])
+    kernels = profile_table(L, ctx, names + [f"{k}_n{n_rhs}" for k in names] + ["blas"])
     L.lq_profile(ctx, False)
-    dom = max((k for k in kernels if k.startswith("stag16")), key=lambda k: kernels[k]["total_ms"])
+    dom = max((k for k in kernels if k.startswith("stag16") and "_n" not in k), key=lambda k: kernels[k]["total_ms"])
     Vh = int(np.prod(HISQ_LAT)) // 2
-    # the profile averages every launch of the kernel: the 12-column multi-shift
-    # ones and the 96-column (8 masses x 12) refinement ones; bytes are counted
-    # for 12 columns, so this figure is a lower bound
-    roof = roofline_for(kernels, dom, stag_site_bytes(16, dom.split("_")[1], n_rhs) * Vh)
-    roof["note"] = "average over 12-column and 96-column launches, bytes counted for 12 columns (lower bound)"
+    # roofline from the 12-column launches (the multi-shift stage); the
+    # refinement launches run at other widths
+    kernels_w = {dom: kernels[f"{dom}_n{n_rhs}"]} if f"{dom}_n{n_rhs}" in kernels else kernels
+    roof = roofline_for(kernels_w, dom, stag_site_bytes(16, dom.split("_")[1], n_rhs) * Vh)
+    roof["launches_at_12_columns"] = kernels_w[dom]["count"]
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline")

@@ -431,7 +431,12 @@ static int run_wilson(OpEnv& e, WilsonArgs& A, int n_fields, int clov_mats, int 
   const bool blocked = !A.dag && (A.epi == EPI_CLOVINV || A.epi == EPI_XMY_CLOVINV || A.epi == EPI_XPAY ||
                                   A.epi == EPI_XPAY_G5 || A.epi == EPI_CHEB || A.epi == EPI_XMY_RTS);
   const int out_npar = A.out.npar;
+  // timed under the kernel's name and under name_n<columns> (solvers that drop
+  // converged columns launch the same kernel at several widths)
+  char name_n[64];
+  snprintf(name_n, sizeof(name_n), "%s_n%d", name, A.ncol);
   Prof p(e.ctx, name, e.s);
+  Prof pn(e.ctx, name_n, e.s);
   int r = tuned(e.ctx, key, A, tune_out_bytes(A.prec, 12, A.ncol, out_npar, A.g.Vh), A.prec,
                 nr_candidates(A.prec, A.ncol, blocked), e.s,
                 [](const WilsonArgs& B, hipStream_t st) { return launch_wilson(B, st); });
@@ -723,7 +728,12 @@ static int run_stag(OpEnv& e, StagArgs& A, int n_fields) {
   std::vector<int> nrs{1};
   for (int nr : {2, 3, 4, 6, 8})
     if (nr <= A.ncol && !(A.prec == 64 && nr > 4)) nrs.push_back(nr);
+  // timed under the kernel's name and under name_n<columns> (solvers that drop
+  // converged columns launch the same kernel at several widths)
+  char name_n[64];
+  snprintf(name_n, sizeof(name_n), "%s_n%d", name, A.ncol);
   Prof p(e.ctx, name, e.s);
+  Prof pn(e.ctx, name_n, e.s);
   if (tuned(e.ctx, key, A, tune_out_bytes(A.prec, 3, A.ncol, A.out.npar, A.g.Vh), A.prec, nrs, e.s,
             [](const StagArgs& B, hipStream_t st) { return launch_stag(B, st); }))
     return fail(LQ_EDEVICE, "staggered stencil launch");

@@ -69,6 +69,57 @@ struct ColParam {
   }
 };
 
+// Keeps the active columns of a batched solver in slots [0, na): a converged
+// column is exchanged with the last active one in every listed vector, in the
+// solver state and in the per-column host arrays and operator parameters.
+// The exchanges applied to the caller's x and b are undone by restore().
+struct Compactor {
+  State& st;
+  Vec& x;
+  Vec& b;
+  std::vector<Vec*> vecs;                    // solver-owned vectors that carry column data
+  std::vector<std::vector<double>*> arrays;  // per-column host values
+  ColParam* cp = nullptr;
+  int na = 0;
+  std::vector<std::pair<int, int>> swaps;
+
+  int swap(int a, int c) {
+    if (a == c) return 0;
+    int e = 0;
+    if ((e = vec_swap_cols(x, a, c)) || (e = vec_swap_cols(b, a, c))) return e;
+    for (Vec* v : vecs)
+      if ((e = vec_swap_cols(*v, a, c))) return e;
+    for (int k = 0; k < ST_STRIDE; ++k) std::swap(st.h(a, k), st.h(c, k));
+    for (auto* arr : arrays) std::swap((*arr)[a], (*arr)[c]);
+    if (cp) std::swap(cp->host[a], cp->host[c]);
+    swaps.emplace_back(a, c);
+    return 0;
+  }
+  // moves columns whose ST_ACTIVE is 0 behind the active ones (the host state
+  // must be current for [0, na)); pushes the state and the parameters
+  int compact() {
+    int e = 0;
+    for (int c = na - 1; c >= 0; --c) {
+      if (st.h(c, ST_ACTIVE) != 0.0) continue;
+      if ((e = swap(c, na - 1))) return e;
+      --na;
+    }
+    if ((e = st.push())) return e;
+    if (cp && (e = cp->upload())) return e;
+    return 0;
+  }
+  int restore() {
+    int e = 0;
+    for (auto it = swaps.rbegin(); it != swaps.rend(); ++it) {
+      if ((e = vec_swap_cols(x, it->first, it->second)) || (e = vec_swap_cols(b, it->first, it->second))) return e;
+      if (cp) std::swap(cp->host[it->first], cp->host[it->second]);
+    }
+    if (cp && !swaps.empty() && (e = cp->upload())) return e;
+    swaps.clear();
+    return 0;
+  }
+};
+
 // Mixed-precision CG with reliable updates on a Hermitian positive-definite A.
 // x, b: FP64.  Columns stop when the FP64 residual of A meets tol[c] |b_c|.
 // Converged columns are moved behind the active ones (columns of every
@@ -104,32 +155,11 @@ int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int pl
     return 0;
   };
   std::vector<double> maxrr(n);
-  std::vector<std::pair<int, int>> swaps;  // applied to x and b, undone at the end
-  // exchange slots a and b of every per-column object (host state must be current)
-  auto swap_slots = [&](int a, int c) -> int {
-    if (a == c) return 0;
-    int rr = 0;
-    for (Vec* v : {&x, &b, &r, &rs, &p, &xs})
-      if ((rr = vec_swap_cols(*v, a, c))) return rr;
-    for (int k = 0; k < ST_STRIDE; ++k) std::swap(st.h(a, k), st.h(c, k));
-    std::swap(bb[a], bb[c]);
-    std::swap(tol[a], tol[c]);
-    std::swap(maxrr[a], maxrr[c]);
-    if (cp) std::swap(cp->host[a], cp->host[c]);
-    swaps.emplace_back(a, c);
-    return 0;
-  };
-  // move the inactive columns behind the active ones; returns the new na
+  Compactor cm{st, x, b, {&r, &rs, &p, &xs}, {&bb, &tol, &maxrr}, cp, n, {}};
   auto compact = [&]() -> int {
-    int rr = 0;
-    for (int c = na - 1; c >= 0; --c) {
-      if (st.h(c, ST_ACTIVE) != 0.0) continue;
-      if ((rr = swap_slots(c, na - 1))) return rr;
-      --na;
-    }
-    if ((rr = st.push())) return rr;
-    if (cp && (rr = cp->upload())) return rr;
-    return 0;
+    const int e2 = cm.compact();
+    na = cm.na;
+    return e2;
   };
   for (int c = 0; c < n; ++c) {
     for (int k = 0; k < ST_STRIDE; ++k) st.h(c, k) = 0.0;
@@ -215,11 +245,7 @@ int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int pl
   }
   const int left = na;
   // original column order of x and b (and of the caller's column parameters)
-  for (auto it2 = swaps.rbegin(); it2 != swaps.rend(); ++it2) {
-    if ((e = vec_swap_cols(x, it2->first, it2->second)) || (e = vec_swap_cols(b, it2->first, it2->second))) return e;
-    if (cp) std::swap(cp->host[it2->first], cp->host[it2->second]);
-  }
-  if (cp && !swaps.empty() && (e = cp->upload())) return e;
+  if ((e = cm.restore())) return e;
   cnt.iters += it;
   return left > 0 ? LQ_ENOCONV : LQ_OK;
 }
@@ -230,7 +256,7 @@ int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int pl
 using FusedFn = std::function<int(Vec& out, const Vec& in, int mode, double* red)>;
 
 int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int plo, Vec& x, Vec& b,
-                   const std::vector<double>& tol, int maxiter, double delta, Counters& cnt,
+                   const std::vector<double>& tol_in, int maxiter, double delta, Counters& cnt,
                    const FusedFn* M_fused = nullptr) {
   const int n = b.ncol, nc = b.nc, npar = b.npar, par0 = b.par0;
   hipStream_t s = bl.s;
@@ -248,13 +274,19 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
   State st(n, s);
   if (!r.ok() || !q64.ok() || !rs.ok() || !rhat.ok() || !p.ok() || !v.ok() || !t.ok() || !xs.ok() || !st.ok())
     return fail(LQ_ENOMEM, "bicgstab buffers");
-  std::vector<double> bb;
+  std::vector<double> bb, tol(tol_in);
   int e = col_norms(bl, b, bb);
   if (e) return e;
+  std::vector<double> maxrr(n);
+  // active columns occupy slots [0, cm.na); v carries column data from one
+  // iteration's M p into the same iteration's p update, across a compaction
+  Compactor cm{st, x, b, {&rs, &rhat, &p, &v, &xs}, {&bb, &tol, &maxrr}, nullptr, n, {}};
+  auto V = [&](Vec& f) { return view(f, 0, cm.na); };
   auto true_res = [&]() -> int {
-    int rr = M_hi(q64, x);
+    Vec qv = V(q64), xv = V(x), bv = V(b);
+    int rr = M_hi(qv, xv);
     if (rr) return rr;
-    if ((rr = bl.op(OP_XMY_NORM, &b, &q64))) return rr;
+    if ((rr = bl.op(OP_XMY_NORM, &bv, &qv))) return rr;
     std::swap(r, q64);
     return 0;
   };
@@ -262,9 +294,10 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
   auto restart = [&]() -> int {
     int rr = true_res();
     if (rr) return rr;
-    if ((rr = vec_copy(rs, r)) || (rr = vec_copy(rhat, r)) || (rr = vec_copy(p, r))) return rr;
-    if ((rr = bl.op(OP_DOT_NORM, &rs, &rhat))) return rr;
-    if (launch_scalar(SC_SET_RHO_RR, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    Vec rv = V(r), rsv = V(rs), rhv = V(rhat), pv = V(p);
+    if ((rr = vec_copy(rsv, rv)) || (rr = vec_copy(rhv, rv)) || (rr = vec_copy(pv, rv))) return rr;
+    if ((rr = bl.op(OP_DOT_NORM, &rsv, &rhv))) return rr;
+    if (launch_scalar(SC_SET_RHO_RR, bl.partial, bl.gridx, cm.na, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
     return 0;
   };
   for (int c = 0; c < n; ++c) {
@@ -275,43 +308,41 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
   if ((e = vec_zero(xs))) return e;
   if ((e = restart())) return e;
   if ((e = st.pull())) return e;
-  std::vector<double> maxrr(n);
-  int nactive = 0;
   for (int c = 0; c < n; ++c) {
     maxrr[c] = st.h(c, ST_RR);
     const bool act = st.h(c, ST_RR) > tol[c] * tol[c] * bb[c] && bb[c] > 0;
     st.h(c, ST_ACTIVE) = act ? 1.0 : 0.0;
-    nactive += act;
   }
-  if ((e = st.push())) return e;
+  if ((e = cm.compact())) return e;
   bool dirty = false;
   int it = 0;
-  for (; it < maxiter && nactive > 0; ++it) {
-    // <rhat, v> by a separate pass: fused into the stencil (mode 1) it measured
-    // slower than the pass, since the extra rhat stream raises the register
-    // pressure of the already heaviest epilogue
-    if ((e = M_lo(v, p))) return e;
-    if ((e = bl.op(OP_DOT, &rhat, &v))) return e;
-    if (launch_scalar(SC_BICG_ALPHA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
-    if ((e = bl.op(OP_AXMY, &v, &rs, nullptr, nullptr, nullptr, st.d(), ST_ALPHA, ST_ALPHA))) return e;
+  for (; it < maxiter && cm.na > 0; ++it) {
+    const int na = cm.na;
+    Vec pv = V(p), vv = V(v), tv = V(t), rsv = V(rs), rhv = V(rhat), xsv = V(xs);
+    // <rhat, v> by a separate pass: fused into the stencil it measured slower
+    // than the pass, since the extra rhat stream raises the register pressure
+    // of the already heaviest epilogue
+    if ((e = M_lo(vv, pv))) return e;
+    if ((e = bl.op(OP_DOT, &rhv, &vv))) return e;
+    if (launch_scalar(SC_BICG_ALPHA, bl.partial, bl.gridx, na, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if ((e = bl.op(OP_AXMY, &vv, &rsv, nullptr, nullptr, nullptr, st.d(), ST_ALPHA, ST_ALPHA))) return e;
     if (M_fused) {
       // <t, s> and |t|^2 computed by the stencil that produces t = M s
-      if ((e = (*M_fused)(t, rs, 2, redbuf.as<double>()))) return e;
-      if (launch_scalar(SC_BICG_OMEGA, redbuf.as<double>(), fused_tiles, n, st.d(), s))
+      if ((e = (*M_fused)(tv, rsv, 2, redbuf.as<double>()))) return e;
+      if (launch_scalar(SC_BICG_OMEGA, redbuf.as<double>(), fused_tiles, na, st.d(), s))
         return fail(LQ_EDEVICE, "scalar");
     } else {
-      if ((e = M_lo(t, rs))) return e;
-      if ((e = bl.op(OP_DOT_NORM, &t, &rs))) return e;
-      if (launch_scalar(SC_BICG_OMEGA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+      if ((e = M_lo(tv, rsv))) return e;
+      if ((e = bl.op(OP_DOT_NORM, &tv, &rsv))) return e;
+      if (launch_scalar(SC_BICG_OMEGA, bl.partial, bl.gridx, na, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
     }
-    if ((e = bl.op(OP_BICG_XR, &p, &rs, &t, &xs, &rhat, st.d(), ST_ALPHA, ST_OMEGA))) return e;
-    if (launch_scalar(SC_BICG_BETA, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if ((e = bl.op(OP_BICG_XR, &pv, &rsv, &tv, &xsv, &rhv, st.d(), ST_ALPHA, ST_OMEGA))) return e;
+    if (launch_scalar(SC_BICG_BETA, bl.partial, bl.gridx, na, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
     dirty = true;
-    if ((e = st.pull())) return e;
+    if ((e = st.pull(na))) return e;
     bool breakdown = false;
     UpdateRule rule;
-    for (int c = 0; c < n; ++c) {
-      if (st.h(c, ST_ACTIVE) == 0.0) continue;
+    for (int c = 0; c < na; ++c) {
       if (st.h(c, ST_FLAG) == 2.0) return fail(LQ_ENUMERIC, "NaN/Inf in a BiCGStab reduction");
       if (st.h(c, ST_FLAG) == 1.0) breakdown = true;
       const double rr = st.h(c, ST_RR);
@@ -322,43 +353,45 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
     const bool update = rule.fire();
     if (update || breakdown || it == maxiter - 1) {
       ++cnt.reliable;
-      if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, n, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
-      if ((e = vec_zero(xs))) return e;
+      if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, na, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
+      if ((e = vec_zero(xsv))) return e;
       dirty = false;
       if (breakdown) {
         ++cnt.restarts;
         if (cnt.restarts > 20) return fail(LQ_EBREAKDOWN, "BiCGStab breakdown persists after restarts");
-        for (int c = 0; c < n; ++c) st.h(c, ST_FLAG) = 0.0;
-        if ((e = st.push())) return e;
+        for (int c = 0; c < na; ++c) st.h(c, ST_FLAG) = 0.0;
+        if ((e = st.push(na))) return e;
         if ((e = restart())) return e;
       } else {
         if ((e = true_res())) return e;
-        if ((e = vec_copy(rs, r))) return e;
-        if ((e = bl.op(OP_DOT_NORM, &rs, &rhat))) return e;
-        if (launch_scalar(SC_SET_RHO_RR, bl.partial, bl.gridx, n, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+        Vec rv = V(r);
+        if ((e = vec_copy(rsv, rv))) return e;
+        if ((e = bl.op(OP_DOT_NORM, &rsv, &rhv))) return e;
+        if (launch_scalar(SC_SET_RHO_RR, bl.partial, bl.gridx, na, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
       }
-      if ((e = st.pull())) return e;
-      nactive = 0;
-      for (int c = 0; c < n; ++c) {
+      if ((e = st.pull(na))) return e;
+      for (int c = 0; c < na; ++c) {
         const double rr = st.h(c, ST_RR);
         maxrr[c] = rr;
-        if (st.h(c, ST_ACTIVE) != 0.0 && rr <= tol[c] * tol[c] * bb[c]) st.h(c, ST_ACTIVE) = 0.0;
-        if (st.h(c, ST_ACTIVE) == 0.0) {
-          st.h(c, ST_BETA) = st.h(c, ST_BETA + 1) = 0.0;
-          st.h(c, ST_OMEGA) = st.h(c, ST_OMEGA + 1) = 0.0;
-        }
-        nactive += st.h(c, ST_ACTIVE) != 0.0;
+        if (rr <= tol[c] * tol[c] * bb[c]) st.h(c, ST_ACTIVE) = 0.0;
       }
-      if ((e = st.push())) return e;
+      if ((e = cm.compact())) return e;
       if (breakdown) continue;  // p = r already
     }
-    if ((e = bl.op(OP_BICG_P, &rs, &v, &p, nullptr, nullptr, st.d(), ST_BETA, ST_OMEGA))) return e;
+    if (cm.na == 0) {
+      ++it;
+      break;
+    }
+    Vec rsn = V(rs), vn = V(v), pn = V(p);
+    if ((e = bl.op(OP_BICG_P, &rsn, &vn, &pn, nullptr, nullptr, st.d(), ST_BETA, ST_OMEGA))) return e;
   }
-  if (dirty) {
-    if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, n, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
+  if (dirty && cm.na > 0) {
+    if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, cm.na, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
   }
+  const int left = cm.na;
+  if ((e = cm.restore())) return e;
   cnt.iters += it;
-  return nactive > 0 ? LQ_ENOCONV : LQ_OK;
+  return left > 0 ? LQ_ENOCONV : LQ_OK;
 }
 
 }  // namespace
