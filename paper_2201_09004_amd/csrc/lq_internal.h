@@ -81,12 +81,18 @@ struct lq_field {
 namespace lq {
 
 // ------------------------------------------------------------------ timing
+// Times the work enqueued on stream st during its lifetime (when profiling is
+// on).  The record joins the context's pending list only once its end event
+// is recorded, so flushing the list never touches a record still in use.
 struct Prof {
   lq_ctx* c;
   hipStream_t s;
-  int idx = -1;
+  bool on = false;
+  ProfRec rec;
   Prof(lq_ctx* ctx, const char* name, hipStream_t st);
   ~Prof();
+  Prof(const Prof&) = delete;
+  Prof& operator=(const Prof&) = delete;
 };
 void prof_flush(lq_ctx* c);
 

@@ -20,18 +20,30 @@ Prof::Prof(lq_ctx* ctx, const char* name, hipStream_t st) : c(ctx), s(st) {
     if (!c->event_pool.empty()) {
       ev[k] = c->event_pool.back();
       c->event_pool.pop_back();
-    } else {
-      hipEventCreate(&ev[k]);
+    } else if (hipEventCreate(&ev[k]) != hipSuccess) {
+      (void)hipGetLastError();
+      if (k == 1) c->event_pool.push_back(ev[0]);
+      return;
     }
   }
-  hipEventRecord(ev[0], s);
-  c->pending.push_back({name, ev[0], ev[1]});
-  idx = (int)c->pending.size() - 1;
+  rec = {name, ev[0], ev[1]};
+  on = hipEventRecord(ev[0], s) == hipSuccess;
+  if (!on) {
+    (void)hipGetLastError();
+    c->event_pool.push_back(ev[0]);
+    c->event_pool.push_back(ev[1]);
+  }
 }
 Prof::~Prof() {
-  if (idx < 0) return;
+  if (!on) return;
   std::lock_guard<std::recursive_mutex> lk(c->prof_mtx);
-  hipEventRecord(c->pending[idx].b, s);
+  if (hipEventRecord(rec.b, s) != hipSuccess) {
+    (void)hipGetLastError();
+    c->event_pool.push_back(rec.a);
+    c->event_pool.push_back(rec.b);
+    return;
+  }
+  c->pending.push_back(rec);
   if (c->pending.size() > 8192) prof_flush(c);
 }
 void prof_flush(lq_ctx* c) {

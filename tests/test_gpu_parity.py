@@ -380,3 +380,28 @@ def test_fp16_subnormal_sites_are_flushed(ctx):
         assert rel(out, want) < TOL[16]
     finally:
         L.lq_field_free(f)
+
+
+def test_profile_records_survive_flushes(ctx):
+    """Kernel timing stays consistent when the pending-record list is flushed
+    while several records (kernel name and name with width) are open."""
+    import torch
+    Lx = (4, 4, 4, 8)
+    U, f = _wilson_setup(ctx, Lx, 151)
+    act = L.action(L.LQ_TM_CLOVER, m=-0.0695, mu=0.01, c_sw=1.0509)
+    psi = torch.from_numpy(synth.gaussian_spinor(Lx, 2, 152)).cuda()
+    out = torch.empty_like(psi)
+    try:
+        L.lq_apply(ctx, act, f, L.LQ_OP_SCHUR, 32, psi, out)
+        L.lq_profile(ctx, True)
+        n = 2200  # 2 launches x 2 records per application: past the flush threshold
+        for _ in range(n):
+            L.lq_apply(ctx, act, f, L.LQ_OP_SCHUR, 32, psi, out)
+        torch.cuda.synchronize()
+        cnt, avg = L.lq_profile_get(ctx, "wilson32_clovinv")
+        cnt_n, avg_n = L.lq_profile_get(ctx, "wilson32_clovinv_n2")
+        L.lq_profile(ctx, False)
+        assert cnt == n and cnt_n == n
+        assert avg > 0 and abs(avg - avg_n) < 0.5 * avg
+    finally:
+        L.lq_field_free(f)
