@@ -108,11 +108,12 @@ __host__ __device__ __forceinline__ int64_t tix(int64_t g, int k, int K, int cb,
 // ---------------------------------------------------------------- streaming access
 // Data that a stencil launch touches exactly once (links, site matrices, the
 // output site's own operands and its result) goes through ldx/stx<true>.
-// With LQ_NT set these carry the non-temporal hint, meant to leave L2 to the
-// neighbour spinors (each read by eight sites); on gfx950 the hinted build
-// measured 20-30% slower stencils, so the hint is off by default.
+// LQ_NT selects which of them carry the non-temporal hint, meant to leave L2
+// to the neighbour spinors (each read by eight sites).  On gfx950 hinted loads
+// made the stencils 20-30% slower, hinted stores 2-3% faster, so by default
+// only the stores are hinted.
 #ifndef LQ_NT
-#define LQ_NT 0  // bit 0: streaming loads, bit 1: streaming stores (measured slower on gfx950)
+#define LQ_NT 2  // bit 0: streaming loads, bit 1: streaming stores
 #endif
 template <bool NT, typename T>
 __device__ __forceinline__ T ldx(const T* p) {

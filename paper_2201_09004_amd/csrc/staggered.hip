@@ -13,7 +13,7 @@
 // FP16 links are stored divided by one FP32 scale per field (fat, long).
 // One thread owns one site and NR consecutive columns: the 16 links of a site
 // are loaded once for all NR columns (bitwise-identical per-column results
-// for every NR).
+// for every NR), and the NR neighbour loads of a hop are issued together.
 #include "lq_common.h"
 #include "lq_kernels.h"
 
@@ -29,11 +29,16 @@ __device__ __forceinline__ void stag_hop1(const StagArgs& A, const int c[4], int
   const int nb = nb_cb(c, MU, K, g);
   if constexpr (K > 0) load_link<P, 9>(links, g.Vh, par, MU, cb, U);
   else load_link<P, 9>(links, g.Vh, pin, MU, nb, U);
+  // all NR columns' loads in flight at once (columns past the last are
+  // clamped to a valid one and their results dropped)
+  cx<R> xn[NR][3];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) IO<P, 3>::load(A.in, blk_index(A.in, min(col0 + r, A.ncol - 1), pin), nb, xn[r]);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    if (r < nv) {
-      cx<R> x[3], y[3];
-      IO<P, 3>::load(A.in, blk_index(A.in, col0 + r, pin), nb, x);
+    {
+      const cx<R>* x = xn[r];
+      cx<R> y[3];
       if constexpr (K > 0) {
         su3_mv(U, x, y);
 #pragma unroll
@@ -47,18 +52,33 @@ __device__ __forceinline__ void stag_hop1(const StagArgs& A, const int c[4], int
   }
 }
 
+// Passes the accumulators through an empty asm statement that also clobbers
+// memory: the arithmetic before it is done before it, the loads after it are
+// issued after it (without it the compiler issues every hop's loads first and
+// holds all neighbours in registers).
+template <int NR, typename R>
+__device__ __forceinline__ void pin3(cx<R> (*a)[3]) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) asm volatile("" : "+v"(a[r][i].re), "+v"(a[r][i].im)::"memory");
+}
+
 template <int P, int MU, int NR, typename R>
 __device__ __forceinline__ void stag_dir(const StagArgs& A, const int c[4], int par, int cb, int col0, int nv,
                                          cx<R> (*af)[3], cx<R> (*al)[3]) {
   stag_hop1<P, MU, 1, false, NR>(A, c, par, cb, col0, nv, af);
   stag_hop1<P, MU, -1, false, NR>(A, c, par, cb, col0, nv, af);
+  pin3<NR>(af);
   stag_hop1<P, MU, 3, true, NR>(A, c, par, cb, col0, nv, al);
   stag_hop1<P, MU, -3, true, NR>(A, c, par, cb, col0, nv, al);
+  pin3<NR>(al);
 }
 
 template <int P, int EPI, int NR>
 __global__ void __launch_bounds__(kStencilMaxThreads) stag_kernel(StagArgs A) {
   using R = typename RealOf<P>::T;
+  if (A.ncol <= 0) return;
   const int ngrp = (A.ncol + NR - 1) / NR;
   int par, cb, grp, c[4];
   if (stencil_site(A.g, A.par_out, A.slab, ngrp, A.sh, par, cb, grp, c) != 1) return;

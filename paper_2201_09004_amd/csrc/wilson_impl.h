@@ -217,6 +217,7 @@ wilson_kernel(WilsonArgs A) {
   using R = typename RealOf<P>::T;
   constexpr bool XMY = EPI == EPI_XMY_CLOVINV || EPI == EPI_XMY_RTS;
   constexpr bool RED = EPI == EPI_XMY_RTS;
+  if (A.ncol <= 0) return;
   const int ngrp = (A.ncol + NR - 1) / NR;
   int par, cb, grp, c[4], tile = 0;
   const int status = stencil_site(A.g, A.par_out, A.slab, ngrp, A.sh, par, cb, grp, c, &tile);
