@@ -105,7 +105,9 @@ enum {
 typedef struct {
   double tol;              /* target relative true residual ||b - D x|| / ||b|| (FP64) */
   int32_t maxiter;         /* iteration cap of the main Krylov loop (0: 10000) */
-  int32_t sloppy_bits;     /* 64, 32 or 16: storage of the inner iterations */
+  int32_t sloppy_bits;     /* 64, 32 or 16: storage of the inner iterations (HISQ
+                              multi-shift with 16: the multi-shift stage runs in FP32
+                              to 1e-8, the per-shift refinement in FP16) */
   double reliable_delta;   /* reliable update when ||r|| < delta * max ||r|| since the last one (0: 0.1) */
   int32_t n_shift;         /* HISQ multi-shift: number of masses (0 or 1: single mass = action.m) */
   const double *masses;    /* HISQ multi-shift: n_shift masses (host) */
