@@ -325,6 +325,9 @@ int launch_scalar(int op, const double* partial, int gridx, int ncol, double* st
 
 // ------------------------------------------------------------ multi-shift CG
 // shift state [i][j][8]: 0 zeta, 1 zeta_old, 2 alpha_i, 3 beta_i, 4 active, 5 zeta_new
+// One iteration: ms_xr (r -= alpha A p and |r|^2, base columns only), the
+// beta step, then ms_p (x_i += alpha_i p_i and p_i = zeta_i r + beta_i p_i,
+// every shift: one pass over p_i serves both updates).
 // base state (per rhs j): ST_ALPHA, ST_BETA, ST_RR, ST_AUX = alpha_old, ST_AUX+1 = beta_old, ST_RR0 = |b|^2,
 // ST_PAD = tol^2 of the multi-shift stage
 enum { MS_Z = 0, MS_ZO, MS_A, MS_B, MS_ACT, MS_ZN };
@@ -349,18 +352,6 @@ __global__ void __launch_bounds__(256) ms_xr_kernel(MsArgs A) {
     IOt::store(A.r, bj, cb, r);
     IOt::load(A.r, bj, cb, r);
     red[0] += norm_acc<R, NC>(r);
-    for (int i = 0; i < A.nshift; ++i) {
-      const double* sh = A.sh + ((int64_t)i * A.nrhs + j) * 8;
-      if (sh[MS_ACT] == 0.0) continue;
-      const R ai = (R)sh[MS_A];
-      const int64_t bi = ((int64_t)i * A.nrhs + j) * A.npar + par;
-      cx<R> x[NC], p[NC];
-      IOt::load(A.p, bi, cb, p);
-      IOt::load(A.x, bi, cb, x);
-#pragma unroll
-      for (int k = 0; k < NC; ++k) x[k] = x[k] + ai * p[k];
-      IOt::store(A.x, bi, cb, x);
-    }
   }
   block_reduce_store<1>(red, A.partial + ((int64_t)j * gridDim.x + blockIdx.x) * 4);
 }
@@ -378,14 +369,26 @@ __global__ void __launch_bounds__(256) ms_p_kernel(MsArgs A) {
     IOt::load(A.r, (int64_t)j * A.npar + par, cb, r);
     for (int i = 0; i < A.nshift; ++i) {
       const double* sh = A.sh + ((int64_t)i * A.nrhs + j) * 8;
-      if (sh[MS_ACT] == 0.0) continue;
-      const R z = (R)sh[MS_Z], b = (R)sh[MS_B];
+      // alpha_i is zero for shifts inactive at this iteration's alpha step; a
+      // shift retired by this iteration's beta step still takes its x step
+      const bool xs = sh[MS_A] != 0.0, ps = sh[MS_ACT] != 0.0;
+      if (!xs && !ps) continue;
+      const R ai = (R)sh[MS_A], z = (R)sh[MS_Z], b = (R)sh[MS_B];
       const int64_t bi = ((int64_t)i * A.nrhs + j) * A.npar + par;
       cx<R> p[NC];
       IOt::load(A.p, bi, cb, p);
+      if (xs) {
+        cx<R> x[NC];
+        IOt::load(A.x, bi, cb, x);
 #pragma unroll
-      for (int k = 0; k < NC; ++k) p[k] = z * r[k] + b * p[k];
-      IOt::store(A.p, bi, cb, p);
+        for (int k = 0; k < NC; ++k) x[k] = x[k] + ai * p[k];
+        IOt::store(A.x, bi, cb, x);
+      }
+      if (ps) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) p[k] = z * r[k] + b * p[k];
+        IOt::store(A.p, bi, cb, p);
+      }
     }
   }
 }

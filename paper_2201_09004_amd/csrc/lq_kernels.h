@@ -130,8 +130,8 @@ struct MsArgs {
   double* partial;
   int gridx;
 };
-int launch_ms_xr(const MsArgs& A, hipStream_t s);     // x_i += a_i p_i ; r -= a Ap ; red |r|^2
-int launch_ms_p(const MsArgs& A, hipStream_t s);      // p_0 = r + b p_0 ; p_i = z_i r + b_i p_i
+int launch_ms_xr(const MsArgs& A, hipStream_t s);     // r -= a Ap ; red |r|^2
+int launch_ms_p(const MsArgs& A, hipStream_t s);      // x_i += a_i p_i ; p_i = z_i r + b_i p_i (p_0: z = 1)
 int launch_ms_scalar_alpha(const MsArgs& A, const double* sigma, hipStream_t s);
 int launch_ms_scalar_beta(const MsArgs& A, hipStream_t s);
 int launch_ms_init(const MsArgs& A, hipStream_t s);
