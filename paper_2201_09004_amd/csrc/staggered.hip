@@ -64,14 +64,21 @@ __device__ __forceinline__ void pin3(cx<R> (*a)[3]) {
     for (int i = 0; i < 3; ++i) asm volatile("" : "+v"(a[r][i].re), "+v"(a[r][i].im)::"memory");
 }
 
+// the backward (x - mu, x - 3 mu) and the forward (x + mu, x + 3 mu) hops of one direction
 template <int P, int MU, int NR, typename R>
-__device__ __forceinline__ void stag_dir(const StagArgs& A, const int c[4], int par, int cb, int col0, int nv,
-                                         cx<R> (*af)[3], cx<R> (*al)[3]) {
-  stag_hop1<P, MU, 1, false, NR>(A, c, par, cb, col0, nv, af);
+__device__ __forceinline__ void stag_back(const StagArgs& A, const int c[4], int par, int cb, int col0, int nv,
+                                          cx<R> (*af)[3], cx<R> (*al)[3]) {
+  stag_hop1<P, MU, -3, true, NR>(A, c, par, cb, col0, nv, al);
   stag_hop1<P, MU, -1, false, NR>(A, c, par, cb, col0, nv, af);
   pin3<NR>(af);
+  pin3<NR>(al);
+}
+template <int P, int MU, int NR, typename R>
+__device__ __forceinline__ void stag_fwd(const StagArgs& A, const int c[4], int par, int cb, int col0, int nv,
+                                         cx<R> (*af)[3], cx<R> (*al)[3]) {
+  stag_hop1<P, MU, 1, false, NR>(A, c, par, cb, col0, nv, af);
   stag_hop1<P, MU, 3, true, NR>(A, c, par, cb, col0, nv, al);
-  stag_hop1<P, MU, -3, true, NR>(A, c, par, cb, col0, nv, al);
+  pin3<NR>(af);
   pin3<NR>(al);
 }
 
@@ -89,10 +96,17 @@ __global__ void __launch_bounds__(kStencilMaxThreads) stag_kernel(StagArgs A) {
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int a = 0; a < 3; ++a) af[r][a] = al[r][a] = {0, 0};
-  stag_dir<P, 0, NR>(A, c, par, cb, col0, nv, af, al);
-  stag_dir<P, 1, NR>(A, c, par, cb, col0, nv, af, al);
-  stag_dir<P, 2, NR>(A, c, par, cb, col0, nv, af, al);
-  stag_dir<P, 3, NR>(A, c, par, cb, col0, nv, af, al);
+  // backward hops from t down to x, then forward hops from x up to t: a
+  // neighbour read as +mu by one wave is read as -mu by a wave started
+  // later, and this order brings the two reads closer in time (L2 hits)
+  stag_back<P, 3, NR>(A, c, par, cb, col0, nv, af, al);
+  stag_back<P, 2, NR>(A, c, par, cb, col0, nv, af, al);
+  stag_back<P, 1, NR>(A, c, par, cb, col0, nv, af, al);
+  stag_back<P, 0, NR>(A, c, par, cb, col0, nv, af, al);
+  stag_fwd<P, 0, NR>(A, c, par, cb, col0, nv, af, al);
+  stag_fwd<P, 1, NR>(A, c, par, cb, col0, nv, af, al);
+  stag_fwd<P, 2, NR>(A, c, par, cb, col0, nv, af, al);
+  stag_fwd<P, 3, NR>(A, c, par, cb, col0, nv, af, al);
   const R kf = (R)(A.k_hop * A.sfat), kl = (R)(A.k_hop * A.slong);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
