@@ -286,7 +286,7 @@ static void tune_save(lq_ctx* c) {
 }
 
 // Traversal orders worth trying for a lattice: lexicographic, z slabs of
-// 1-8 planes, the (y, z, t) blocks of whole x rows with the least surface
+// 1-8 planes, and the (y, z, t) blocks of whole x rows with the least surface
 // per site among those of 1.5k-6k sites (about what one XCD has in flight).
 static std::vector<int> slab_candidates(const Geom& g) {
   std::vector<int> v{0};
@@ -432,7 +432,7 @@ static std::vector<int> nr_candidates(int prec, int ncol, bool blocked) {
 
 static int run_wilson(OpEnv& e, WilsonArgs& A, int n_fields, int clov_mats, int flops_extra) {
   A.g = e.f->g;
-  if (A.ncol <= 0) return 0;  // nothing to compute (the kernels read column ncol - 1)
+  if (A.ncol <= 0) return 0;  // nothing to compute
   A.recon = (e.recon && A.prec != 64) ? 1 : 0;
   if (!A.links) return fail(LQ_EDEVICE, "links not packed");
   const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
