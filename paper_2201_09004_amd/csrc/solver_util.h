@@ -4,6 +4,7 @@
 #pragma once
 
 #include <algorithm>
+#include <cmath>
 #include <functional>
 #include <vector>
 
@@ -71,6 +72,21 @@ struct UpdateRule {
   }
   bool fire() const { return now || (active > 0 && 2 * due >= active); }
 };
+
+// Iterations until a column's squared residual rr reaches the next threshold
+// of UpdateRule (due at delta^2 maxrr, then convergence or delta^4 maxrr),
+// predicted from its mean reduction per iteration since the previous host
+// check (rr_prev, steps iterations ago); 0 when it is not decreasing.  A
+// solver that reads its state every iteration only to evaluate the rule can
+// skip the reads for about half the smallest such count.
+inline double iters_to_event(double rr, double rr_prev, int steps, double maxrr, double tol2bb, double delta) {
+  const double d2 = delta * delta;
+  const double t = std::max(tol2bb, rr >= d2 * maxrr ? d2 * maxrr : d2 * d2 * maxrr);
+  if (!(rr > t) || !(rr_prev > 0.0) || steps <= 0) return 0.0;
+  const double f = std::pow(rr / rr_prev, 1.0 / steps);
+  if (!(f < 0.999)) return 0.0;
+  return std::log(t / rr) / std::log(f);
+}
 
 // per-column |v|^2 (host vector)
 int col_norms(Blas& bl, Vec& v, std::vector<double>& out);
