@@ -226,6 +226,24 @@ def test_wilson_cgne_fp64(ctx):
         L.lq_field_free(f)
 
 
+def test_wilson_cgne_fp32_sloppy_deferred_checks(ctx):
+    """CG on the normal equations with FP32 sloppy vectors and FP64 reliable
+    updates, three columns: the host reads the residual norms only every few
+    iterations (predicted from each column's decay), and every column still
+    reaches the FP64 target with the oracle operator."""
+    Lx = (4, 4, 6, 8)
+    U, f = _wilson_setup(ctx, Lx, 85, eps=0.3)
+    m = 1.0 / (2 * 0.125) - 4.0
+    b = synth.gaussian_spinor(Lx, 3, 86)
+    try:
+        x, st = L.lq_solve(ctx, L.action(L.LQ_WILSON, m=m), f, L.params(tol=1e-10, sloppy_bits=32), b)
+        assert st["status"] == 0 and st["true_rel_res"] <= 1e-10
+        assert st["reliable_updates"] >= 2
+        assert _resid(lambda v: W.wilson(U, v, m), x, b) < 1e-10
+    finally:
+        L.lq_field_free(f)
+
+
 @pytest.mark.parametrize("sloppy,fused", [(64, True), (32, True), (32, False)])
 def test_tm_clover_eo_bicgstab(ctx, sloppy, fused, monkeypatch):
     """Even-odd BiCGStab, with the BiCGStab reductions fused into the Schur
