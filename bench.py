@@ -359,7 +359,8 @@ def bench_hisq(args, L, torch):
     wide = [k for k in kernels if k.startswith(("stag16", "stag32")) and k.endswith(f"_n{n_rhs}")]
     dom_n = max(wide, key=lambda k: kernels[k]["total_ms"])
     dom = dom_n[: -len(f"_n{n_rhs}")]
-    roof = roofline_for({dom: kernels[dom_n]}, dom, stag_site_bytes(int(dom[4:6]), dom.split("_")[1], n_rhs) * Vh)
+    roof = roofline_for({dom: kernels[dom_n]}, dom, stag_site_bytes(int(dom[4:6]), dom.split("_")[1], n_rhs) * Vh,
+                        measured_traffic(dom, "hisq_multishift_cg_32x32x32x96_12rhs_8mass"))
     roof["launches_at_12_columns"] = kernels[dom_n]["count"]
     cpu = None
     if not args.no_cpu:
