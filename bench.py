@@ -484,7 +484,7 @@ def bench_overlap(args, L, torch):
     Vh = int(np.prod(OV_LAT)) // 2
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"] if k != "blas" else -1)
     alg = wilson_site_bytes(16, "cheb" if dom.endswith("cheb") else "xpay_g5", n_rhs) * 2 * Vh
-    roof = roofline_for(kernels, dom, alg)
+    roof = roofline_for(kernels, dom, alg, measured_traffic(dom, "overlap_sign_cheb200_24x24x24x64_12rhs"))
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline")
