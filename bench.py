@@ -12,9 +12,14 @@ Other workloads (--workload):
   hisq     multi-shift CG for 8 masses 0.002..0.05 (log-spaced) on 32^3 x 96
            (the MILC09 shape), 12 colour point sources, FP16 sloppy storage,
            per-shift refinement to 1e-10 (sec. 2.2, Table 3)
-  overlap  the order-200 Chebyshev sign function eps(H_W) applied to 12
-           columns on 24^3 x 64 (the RBC11 shape, rho = 1.5), FP16 storage
-           (sec. 2.3, Fig. 2); one step = one eps application
+  overlap  the overlap propagator on 24^3 x 64 (the RBC11 shape, rho = 1.5,
+           m = 0.015): 12 point sources solved to 1e-10 with the chirally
+           projected normal equations, the order-200 Chebyshev sign function
+           in FP16 storage and FP64 reliable updates (sec. 2.3, eq. 5)
+  overlap_mm  the same propagator for the masses 0.03, 0.05, 0.10 to 1e-8
+           (multi-shift CG in the chiral sector, then per-mass refinement)
+  overlap_sign  one application of the order-200 sign function eps(H_W) to
+           12 columns in FP16 storage (sec. 2.3, Fig. 2)
   serve    the serving loop: Poisson arrivals of 12-column twisted-clover and
            HISQ requests on 16^3x32, 24^3x64 and 32^3x64, p50/p99 latency
   wilson   plain Wilson CG on the normal equations, FP64, 8^4, kappa = 0.12
@@ -44,6 +49,7 @@ HISQ_LAT = (32, 32, 32, 96)
 HISQ_MASSES = [0.002 * 25.0 ** (i / 7.0) for i in range(8)]
 OV_LAT = (24, 24, 24, 64)
 OV_RHO, OV_M, OV_N = 1.5, 0.015, 200
+OV_MASSES, OV_MM_TOL = [0.03, 0.05, 0.10], 1e-8  # multi-mass overlap propagators of sec. 2.3
 
 
 def log(*a):
@@ -277,17 +283,24 @@ def bench_tm(args, L, torch):
 
     fp64 = None
     if not args.no_fp64:
+        # the plain FP64 solver on one column: one untimed solve (it also tunes
+        # the one-column launch shapes), then the median of three timed solves
         log("FP64 single-column solve")
         p64 = L.params(tol=1e-10, sloppy_bits=64)
         b1 = b_d[:1].contiguous()
         x1 = torch.zeros_like(b1)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        _, st64 = L.lq_solve(ctx, act, field, p64, b1, x1)
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        fp64 = {"solves_per_s": 1.0 / (tb - ta), "seconds": tb - ta, "iters": st64["iters"],
-                "true_rel_res": st64["true_rel_res"]}
+        L.lq_solve(ctx, act, field, p64, b1, x1)
+        runs = []
+        for _ in range(3):
+            x1.zero_()
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, st64 = L.lq_solve(ctx, act, field, p64, b1, x1)
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - ta)
+        t64 = sorted(runs)[1]
+        fp64 = {"solves_per_s": 1.0 / t64, "seconds_median_of_3": t64, "seconds_all": runs, "iters": st64["iters"],
+                "true_rel_res": st64["true_rel_res"], "warmup": 1}
         log("fp64", fp64)
     cpu = None
     if not args.no_cpu:
@@ -440,7 +453,7 @@ def bench_wilson(args, L, torch):
     }
 
 
-def bench_overlap(args, L, torch):
+def bench_overlap_sign(args, L, torch):
     import numpy as np
 
     import synth
@@ -455,7 +468,7 @@ def bench_overlap(args, L, torch):
     ctx = L.lq_init(0)
     field = L.lq_gauge_load(ctx, OV_LAT, U_d)
     del U_d
-    lo, hi = L.lq_hw_bounds(ctx, L.action(L.LQ_OVERLAP, m=OV_M, rho=OV_RHO), field, 200)
+    lo, hi = L.lq_hw_bounds(ctx, L.action(L.LQ_OVERLAP, m=OV_M, rho=OV_RHO), field, 300)
     a, b = 0.9 * lo * lo, 1.1 * hi * hi
     log("H_W spectrum", lo, hi, "interval", a, b)
     act = L.action(L.LQ_OVERLAP, m=OV_M, rho=OV_RHO, cheb_N=OV_N, cheb_a=a, cheb_b=b)
@@ -500,6 +513,118 @@ def bench_overlap(args, L, torch):
                    "rho": OV_RHO, "N": OV_N, "interval": [a, b], "hw_spectrum": [lo, hi], "storage": "fp16"},
         "roofline": roof, "cpu_baseline": cpu, "fp16_vs_fp32_rel_l2": rel16, "finite": finite, "kernels": kernels,
     }
+
+
+def cpu_overlap_solve(n_eps_per_col: int):
+    """FP64 oracle H_W on a 24^3 x 2 slab, one core: an order-20 sign function
+    (41 H_W products) timed and scaled per H_W product to 24^3 x 64, then to
+    401 products per order-200 sign function and to the sign functions one
+    column of the GPU solve used."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import overlap as O
+
+    slab = (24, 24, 24, 2)
+    U = synth.su3_field(slab, EPS, SEED)
+    v = synth.gaussian_spinor(slab, 1, 7)[0]
+    n = 20
+    c = O.cheb_coeffs(0.3, 48.0, n)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        y = O.sign_hw(U, v, OV_RHO, c, 0.3, 48.0)
+        t1 = time.perf_counter()
+    assert np.isfinite(y).all()
+    scale = OV_LAT[3] / slab[3]
+    t_hw = (t1 - t0) / (2 * n + 1) * scale
+    t_col = t_hw * (2 * OV_N + 1) * n_eps_per_col
+    return {"value": 1.0 / t_col, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 numpy oracle, 1 thread: an order-{n} sign function ({2 * n + 1} H_W products) on "
+                       f"one column of a 24^3x2 slab ({t1 - t0:.1f} s), scaled x{scale:.0f} to 24^3x64, to "
+                       f"{2 * OV_N + 1} H_W per order-{OV_N} sign function and to {n_eps_per_col} sign functions "
+                       f"per column (the GPU solve's count); extrapolated"),
+            "t_hw_s": t_hw}
+
+
+def _overlap_solve_leg(args, L, torch, masses, tol, workload):
+    import numpy as np
+
+    import synth
+
+    dev = torch.device("cuda:0")
+    n_rhs = 12
+    log("generating synthetic gauge field", OV_LAT)
+    U = synth.su3_field(OV_LAT, EPS, SEED)
+    U_d = torch.from_numpy(U).to(dev)
+    del U
+    b_d = torch.from_numpy(synth.point_sources(OV_LAT)).to(dev)
+    ctx = L.lq_init(0)
+    field = L.lq_gauge_load(ctx, OV_LAT, U_d)
+    del U_d
+    torch.cuda.empty_cache()
+    lo, hi = L.lq_hw_bounds(ctx, L.action(L.LQ_OVERLAP, m=OV_M, rho=OV_RHO), field, 300)
+    log("certified H_W interval", lo, hi, "Chebyshev interval", 0.9 * lo * lo, 1.1 * hi * hi)
+    act = L.action(L.LQ_OVERLAP, m=masses[0], rho=OV_RHO, cheb_N=OV_N)
+    prm = L.params(tol=tol, sloppy_bits=16, masses=masses if len(masses) > 1 else None)
+    nm = len(masses)
+    x_d = torch.zeros(((nm,) if nm > 1 else ()) + tuple(b_d.shape), dtype=b_d.dtype, device=dev)
+    for _ in range(args.warmup):
+        _, st = L.lq_solve(ctx, act, field, prm, b_d, x_d)
+        log("warmup stats", st)
+    torch.cuda.synchronize()
+    L.lq_profile(ctx, True)
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = L.lq_solve(ctx, act, field, prm, b_d, x_d)
+        stats.append(st)
+        log("step", st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) / args.steps * 1e3
+    value = n_rhs * args.steps / (t1 - t0)
+    worst = max(s["true_rel_res"] for s in stats)
+    ok = all(s["status"] == 0 for s in stats) and worst <= tol
+    names = [f"wilson{p}_{e}" for p in (16, 32, 64) for e in ("cheb", "xpay_g5")]
+    kernels = profile_table(L, ctx, names + [f"{k}_n{n_rhs}" for k in names] + ["blas"])
+    L.lq_profile(ctx, False)
+    Vh = int(np.prod(OV_LAT)) // 2
+    # dominant kernel by total time; its roofline from its 12-column launches
+    dom = max((k for k in kernels if k.startswith("wilson") and "_n" not in k), key=lambda k: kernels[k]["total_ms"])
+    prec = int(dom[6:8])
+    kw = {dom: kernels[f"{dom}_n{n_rhs}"]} if f"{dom}_n{n_rhs}" in kernels else kernels
+    alg = wilson_site_bytes(prec, "cheb" if dom.endswith("cheb") else "xpay_g5", n_rhs) * 2 * Vh
+    roof = roofline_for(kw, dom, alg, measured_traffic(dom, "overlap_sign_cheb200_24x24x24x64_12rhs"))
+    roof["launches_at_full_width"] = kw[dom]["count"]
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        s0 = stats[0]
+        cpu = cpu_overlap_solve(int(np.ceil((s0["iters"] + s0["reliable_updates"]) * nm / max(nm, 1))) + 3)
+        log("cpu", cpu)
+    L.lq_field_free(field)
+    L.lq_finalize(ctx)
+    return {
+        "metric": METRIC, "value": round(value, 5), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+        "config": {"workload": workload, "lattice": list(OV_LAT), "n_rhs": n_rhs, "rho": OV_RHO, "masses": masses,
+                   "N": OV_N, "hw_interval": [lo, hi], "sources": "point", "links": "exp(i*0.2*H) seed 1001",
+                   "solver": "chirally projected CG, fp16 sign function, fp64 reliable updates", "tol": tol},
+        "roofline": roof, "cpu_baseline": cpu, "converged": ok, "worst_true_rel_res": worst,
+        "iters": [s["iters"] for s in stats], "reliable_updates": [s["reliable_updates"] for s in stats],
+        "mass_columns_per_s": round(value * nm, 5), "kernels": kernels,
+    }
+
+
+def bench_overlap(args, L, torch):
+    return _overlap_solve_leg(args, L, torch, [OV_M], 1e-10, "overlap_chiral_cg_24x24x24x64_12rhs_cheb200_fp16")
+
+
+def bench_overlap_mm(args, L, torch):
+    return _overlap_solve_leg(args, L, torch, OV_MASSES, OV_MM_TOL,
+                              "overlap_multimass_chiral_cg_24x24x24x64_12rhs_3mass_cheb200_fp16")
 
 
 def bench_serve(args, L, torch):
@@ -588,7 +713,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("tm", "hisq", "overlap", "serve", "wilson"), default="tm")
+    ap.add_argument("--workload", choices=("tm", "hisq", "overlap", "overlap_mm", "overlap_sign", "serve", "wilson"),
+                    default="tm")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 single-column comparison")
     ap.add_argument("--recon12", type=int, default=0)
@@ -604,8 +730,8 @@ def main():
     from paper_2201_09004_amd import lq as L
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    fn = {"tm": bench_tm, "hisq": bench_hisq, "overlap": bench_overlap, "serve": bench_serve,
-          "wilson": bench_wilson}[args.workload]
+    fn = {"tm": bench_tm, "hisq": bench_hisq, "overlap": bench_overlap, "overlap_mm": bench_overlap_mm,
+          "overlap_sign": bench_overlap_sign, "serve": bench_serve, "wilson": bench_wilson}[args.workload]
     out = fn(args, L, torch)
     print(json.dumps(out), flush=True)
 

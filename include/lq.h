@@ -82,8 +82,10 @@ typedef struct {
   double c_sw;        /* clover coefficient, TM only (0: no clover term) */
   double rho;         /* overlap: D_W(-rho) kernel, rho ~ 1.5 */
   int32_t cheb_N;     /* overlap: polynomial order in H^2 (2N+1 H_W products) */
-  double cheb_a;      /* overlap: interval [a, b] holding the spectrum of H_W^2 */
-  double cheb_b;      /*   (both 0: the library measures it, see lq_hw_bounds) */
+  double cheb_a;      /* overlap: interval [a, b] holding the spectrum of H_W^2 (both 0: the */
+  double cheb_b;      /*   library takes a = 0.9 lmin^2, b = 1.1 lmax^2 from lq_hw_bounds; a
+                           given interval that excludes a Lanczos Ritz value of H_W^2 is
+                           refused with LQ_EINVAL) */
   const double *cheb_c; /* overlap: N+1 coefficients (host), or NULL: the library
                            interpolates y^(-1/2) at the Chebyshev nodes of [a,b] */
 } lq_action;
@@ -109,13 +111,14 @@ typedef struct {
                               multi-shift with 16: the multi-shift stage runs in FP32
                               to 1e-8, the per-shift refinement in FP16) */
   double reliable_delta;   /* reliable update when ||r|| < delta * max ||r|| since the last one (0: 0.1) */
-  int32_t n_shift;         /* HISQ multi-shift: number of masses (0 or 1: single mass = action.m) */
-  const double *masses;    /* HISQ multi-shift: n_shift masses (host) */
+  int32_t n_shift;         /* HISQ / overlap multi-mass: number of masses (0 or 1: single mass = action.m) */
+  const double *masses;    /* HISQ / overlap multi-mass: n_shift masses (host) */
   int32_t reconstruct_full;/* HISQ: 1 returns x_i = D(m_i)^dag y_i on all sites, 0 returns y_i on even sites */
   int32_t recon12;         /* 1: 12-real link reconstruction in sloppy FP32/FP16 Wilson stencils */
   int32_t use_initial_guess;/* 1: x holds the initial guess on input */
   int32_t fault_inject;    /* testing: 1 NaN in the first reduction, 2 allocation failure, 3 maxiter=1 */
-  int32_t solver;          /* 0: default for the action, 1: CG on normal equations (full lattice) */
+  int32_t solver;          /* 0: default for the action, 1: CG on normal equations D^dag D (full lattice,
+                              twisted clover and overlap) */
 } lq_params;
 
 typedef struct {
@@ -165,17 +168,30 @@ lq_status lq_apply_dev(lq_ctx *ctx, const lq_action *act, const lq_field *g, int
  *   LQ_TM_CLOVER:  even-odd (symmetric Schur) BiCGStab, sloppy storage + FP64 reliable updates
  *   LQ_HISQ:       multi-shift CG on M_e(m_i) = m_i^2 - D_eo D_oe (even sites), then a
  *                  per-shift mixed-precision CG refinement; x is [n_shift][n_rhs][V][3]
- *   LQ_OVERLAP:    CG on D(m)^dag D(m) with FP64 vectors, sloppy sign function and FP64
- *                  reliable updates.
- * x: on input the initial guess if prm->use_initial_guess, on output the solution.
+ *   LQ_OVERLAP:    chirally projected normal equations (sec. 2.3): on a source of chirality
+ *                  s, D(m)^dag D(m) = (1 - m^2/(4 rho^2)) 2 rho^2 (1 + s P_s eps P_s) + m^2
+ *                  needs one sign function per CG iteration; each source is split into
+ *                  its chiral halves (a spin-colour point source has one), the sector
+ *                  system is solved by CG with sloppy storage of the sign function and
+ *                  FP64 reliable updates, x = D(m)^dag z, and the FP64 residual of the
+ *                  full D(m) is corrected by further sector solves until it meets tol.
+ *                  Several masses (n_shift, masses in (0, 2 rho)) share one multi-shift
+ *                  CG (the masses are shifts of the same sector operator), then each is
+ *                  refined; x is [n_shift][n_rhs][V][4][3].  solver = 1: plain CG on
+ *                  D(m)^dag D(m) (two sign functions per iteration), one mass.
+ * x: on input the initial guess if prm->use_initial_guess (one mass), on output the solution.
  * stats may be NULL. */
 lq_status lq_solve(lq_ctx *ctx, const lq_action *act, const lq_field *g, const lq_params *prm, int n_rhs,
                    const double *b, double *x, lq_stats *stats);
 lq_status lq_solve_dev(lq_ctx *ctx, const lq_action *act, const lq_field *g, const lq_params *prm, int n_rhs,
                        const double *b_dev, double *x_dev, lq_stats *stats, void *stream);
 
-/* Extremal |eigenvalues| of H_W = g5 D_W(-rho) by FP64 Lanczos on H_W^2 (sec. 2.3:
- * the Chebyshev interval must hold the spectrum). */
+/* Interval [lmin, lmax] of |eigenvalues| of H_W = g5 D_W(-rho) (sec. 2.3: the
+ * Chebyshev interval must hold the spectrum).  `iters` FP64 Lanczos steps on H_W^2
+ * from a fixed random start give the extreme Ritz values theta and, from the Ritz
+ * vectors, the FP64 residual norms r = |H_W^2 y - theta y|; the result is
+ * lmin^2 = theta_min - r_min, lmax^2 = theta_max + r_max.  LQ_EINVAL when the
+ * smallest Ritz pair has not converged (r_min >= theta_min / 2) or iters < 2. */
 lq_status lq_hw_bounds(lq_ctx *ctx, const lq_action *act, const lq_field *g, int iters, double *lmin,
                        double *lmax);
 /* Coefficients c_0..c_N of the Chebyshev interpolant of y^(-1/2) on [a, b] (host, FP64). */

@@ -221,12 +221,15 @@ static int check_solve(lq_ctx* c, const lq_action* act, const lq_field* g, const
     return fail(LQ_EINVAL, "sloppy_bits must be 64, 32 or 16");
   if (!(prm->tol >= 0) || prm->tol >= 1.0) return fail(LQ_EINVAL, "tol must be in [0, 1)");
   if (prm->n_shift < 0 || prm->n_shift > 64) return fail(LQ_EINVAL, "n_shift out of range");
-  if (prm->n_shift > 1 && act->kind != LQ_HISQ) return fail(LQ_EINVAL, "multi-shift is implemented for HISQ");
+  if (prm->n_shift > 1 && act->kind != LQ_HISQ && act->kind != LQ_OVERLAP)
+    return fail(LQ_EINVAL, "several masses are implemented for HISQ and overlap");
+  if (prm->n_shift > 1 && act->kind == LQ_OVERLAP && prm->solver == 1)
+    return fail(LQ_EINVAL, "overlap: several masses need the chirally projected solver (solver = 0)");
   return 0;
 }
 
 static size_t solution_doubles(const lq_field* g, const lq_action* act, const lq_params* prm, int n_rhs) {
-  const int nsh = (act->kind == LQ_HISQ && prm->n_shift > 1) ? prm->n_shift : 1;
+  const int nsh = ((act->kind == LQ_HISQ || act->kind == LQ_OVERLAP) && prm->n_shift > 1) ? prm->n_shift : 1;
   return (size_t)nsh * field_doubles(g, act->kind, n_rhs);
 }
 

@@ -165,6 +165,15 @@ __global__ void __launch_bounds__(256) blas_kernel(BlasArgs A) {
     } else if constexpr (OP == OP_COPY) {
       IOt::load(A.f[0], blk, cb, a);
       IOt::store(A.f[1], blk, cb, a);
+    } else if constexpr (OP == OP_PLC) {
+      // upper spins see g5 = +1, lower spins g5 = -1
+      const double* q = A.pcol + (int64_t)col * 4;
+      const R p0 = (R)q[0], pu = (R)(q[1] * (q[2] + q[3])), pl = (R)(q[1] * (q[2] - q[3]));
+      IOt::load(A.f[0], blk, cb, a);
+      IOt::load(A.f[1], blk, cb, b);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) a[k] = p0 * a[k] + (k < NC / 2 ? pu : pl) * b[k];
+      IOt::store(A.f[2], blk, cb, a);
     }
   }
   if constexpr (op_reduces(OP)) {
@@ -186,7 +195,7 @@ static void blas_dispatch(const BlasArgs& A, dim3 grid, dim3 block, hipStream_t 
   switch (A.op) {
     LQ_OPC(OP_AXPY) LQ_OPC(OP_AXMY) LQ_OPC(OP_XPAY) LQ_OPC(OP_CG) LQ_OPC(OP_BICG_XR) LQ_OPC(OP_BICG_P)
     LQ_OPC(OP_DOT) LQ_OPC(OP_NORM2) LQ_OPC(OP_DOT_NORM) LQ_OPC(OP_XMY_NORM) LQ_OPC(OP_ZERO) LQ_OPC(OP_SCALE)
-    LQ_OPC(OP_G5) LQ_OPC(OP_LC_G5) LQ_OPC(OP_COPY)
+    LQ_OPC(OP_G5) LQ_OPC(OP_LC_G5) LQ_OPC(OP_COPY) LQ_OPC(OP_PLC)
     default: break;
   }
 #undef LQ_OPC

@@ -62,6 +62,13 @@ struct Clover {
   void* Ainv[2] = {nullptr, nullptr};  // [FP64, FP32] full complex (H +- i mu)^{-1}
 };
 
+// Lanczos estimate of the spectrum of H_W^2: extreme Ritz values and the FP64
+// residual norms of their Ritz vectors
+struct HwSpectrum {
+  double theta_min, theta_max, r_min, r_max;
+  int steps;
+};
+
 }  // namespace lq
 
 struct lq_field {
@@ -75,6 +82,7 @@ struct lq_field {
   void* lng[3] = {nullptr, nullptr, nullptr};
   float sfat[3] = {1, 1, 1}, slng[3] = {1, 1, 1};
   std::map<std::tuple<double, double, double>, lq::Clover> clover;
+  std::map<double, lq::HwSpectrum> hw_spec;  // per rho: Lanczos spectrum of H_W^2
   std::mutex mtx;
 };
 
@@ -191,6 +199,8 @@ struct Blas {
   int op(int opc, Vec* f0, Vec* f1 = nullptr, Vec* f2 = nullptr, Vec* f3 = nullptr, Vec* f4 = nullptr,
          const double* st = nullptr, int c0 = 0, int c1 = 0);
   int opi(int opc, Vec* f0, Vec* f1, Vec* f2, double c0re, double c0im = 0, double c1re = 0, double c1im = 0);
+  // OP_PLC: f2 = p0 f0 + p1 (p2 f1 + p3 g5 f1) with [ncol][4] coefficients pcol (device)
+  int plc(Vec* f0, Vec* f1, Vec* f2, const double* pcol);
 };
 int blas_prepare(lq_ctx* c, Blas& b, const Geom& g, int npar, int ncol, hipStream_t s);
 
@@ -198,6 +208,8 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
           double* x_dev, lq_stats* st, hipStream_t s);
 int apply_op(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec, int n_rhs, const double* in_dev,
              double* out_dev, hipStream_t s);
+int hw_spectrum(lq_ctx* c, const lq_action* act, lq_field* f, int iters, HwSpectrum* out, hipStream_t s);
+// certified interval: lmin^2 = theta_min - r_min, lmax^2 = theta_max + r_max
 int hw_bounds(lq_ctx* c, const lq_action* act, lq_field* f, int iters, double* lmin, double* lmax, hipStream_t s);
 void cheb_coeffs(double a, double b, int N, double* c);
 

@@ -94,6 +94,7 @@ enum {
   OP_G5,         // f1 = g5 f0 (Wilson only)
   OP_LC_G5,      // f2 = c0 f0 + c1 g5 f1 (Wilson only)
   OP_COPY,       // f1 = f0
+  OP_PLC,        // f2 = p0 f0 + p1 (p2 f1 + p3 g5 f1), real p0..p3 per column from pcol (Wilson only)
   OP_NCOUNT
 };
 
@@ -109,6 +110,7 @@ struct BlasArgs {
   double imm[4];     // immediate coefficients c0 = imm[0] + i imm[1], c1 = imm[2] + i imm[3]
   double* partial;   // [ncol][gridx][4]
   int gridx;
+  const double* pcol;  // OP_PLC: [ncol][4] real coefficients (device)
 };
 int launch_blas(const BlasArgs& A, hipStream_t s);
 int blas_gridx(int64_t nsite);

@@ -623,16 +623,45 @@ int hw_apply(OpEnv& e, int prec, Vec& out, const Vec& in) {
   return run_wilson(e, A, 3, 0, 48);
 }
 
+// Lanczos steps for the H_W^2 interval of the Chebyshev approximation
+#ifndef LQ_HW_LANCZOS
+#define LQ_HW_LANCZOS 300
+#endif
+
+// The Chebyshev interval [a, b] must hold the spectrum of H_W^2 (sec. 2.3).
+// The Lanczos spectrum of H_W(rho) is measured once per field and rho.  With
+// no interval given, a = 0.9 (theta_min - r_min) and b = 1.1 (theta_max + r_max)
+// (certified Ritz bounds with a margin); a given interval is refused
+// (LQ_EINVAL) when a Ritz value lies outside it, since Ritz values lie inside
+// the spectrum.
 int overlap_prepare(OpEnv& e) {
   if (!e.cheb.empty()) return 0;
   if (e.act.cheb_N < 1) return fail(LQ_EINVAL, "overlap: cheb_N must be >= 1");
-  double a = e.act.cheb_a, b = e.act.cheb_b;
-  if (!(a > 0 && b > a)) {
-    double lmin = 0, lmax = 0;
-    int r = hw_bounds(e.ctx, &e.act, e.f, 200, &lmin, &lmax, e.s);
+  HwSpectrum sp{};
+  bool have = false;
+  {
+    std::lock_guard<std::mutex> lk(e.f->mtx);
+    auto it = e.f->hw_spec.find(e.act.rho);
+    if (it != e.f->hw_spec.end()) {
+      sp = it->second;
+      have = true;
+    }
+  }
+  if (!have) {
+    int r = hw_spectrum(e.ctx, &e.act, e.f, LQ_HW_LANCZOS, &sp, e.s);
     if (r) return r;
-    a = 0.9 * lmin * lmin;
-    b = 1.1 * lmax * lmax;
+    std::lock_guard<std::mutex> lk(e.f->mtx);
+    e.f->hw_spec[e.act.rho] = sp;
+  }
+  double a = e.act.cheb_a, b = e.act.cheb_b;
+  if (a > 0 && b > a) {
+    if (sp.theta_min < a || sp.theta_max > b)
+      return fail(LQ_EINVAL, "overlap: the Chebyshev interval [" + std::to_string(a) + ", " + std::to_string(b) +
+                                 "] does not hold the spectrum of H_W^2 (Ritz values " +
+                                 std::to_string(sp.theta_min) + ", " + std::to_string(sp.theta_max) + ")");
+  } else {
+    a = 0.9 * (sp.theta_min - sp.r_min);
+    b = 1.1 * (sp.theta_max + sp.r_max);
   }
   e.a = a;
   e.b = b;
@@ -863,6 +892,27 @@ int Blas::opi(int opc, Vec* f0, Vec* f1, Vec* f2, double c0re, double c0im, doub
   A.imm[1] = c0im;
   A.imm[2] = c1re;
   A.imm[3] = c1im;
+  A.partial = partial;
+  A.gridx = gridx;
+  Prof p(ctx, "blas", s);
+  return launch_blas(A, s) ? fail(LQ_EDEVICE, "blas launch") : 0;
+}
+
+int Blas::plc(Vec* f0, Vec* f1, Vec* f2, const double* pcol) {
+  BlasArgs A{};
+  A.prec = f0->prec;
+  A.nc = f0->nc;
+  A.ncol = f0->ncol;
+  A.npar = f0->npar;
+  A.Vh = f0->f.Vh;
+  A.op = OP_PLC;
+  Vec* fs[3] = {f0, f1, f2};
+  for (int k = 0; k < 3; ++k) {
+    if (fs[k]->prec != A.prec || fs[k]->npar != A.npar || fs[k]->ncol < A.ncol || fs[k]->nc != 12)
+      return fail(LQ_EINVAL, "blas: operand shape/precision mismatch");
+    A.f[k] = fs[k]->f;
+  }
+  A.pcol = pcol;
   A.partial = partial;
   A.gridx = gridx;
   Prof p(ctx, "blas", s);

@@ -10,6 +10,8 @@
 // the FP64 operator of the full (unpreconditioned) system, meets the target.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <random>
 
@@ -27,6 +29,16 @@
 
 namespace lq {
 
+
+// LQ_VERBOSE=1: the solvers report each reliable update and each overlap
+// correction pass on stderr (progress of long solves)
+static bool verbose() {
+  static const bool v = [] {
+    const char* e = getenv("LQ_VERBOSE");
+    return e && *e && *e != '0';
+  }();
+  return v;
+}
 
 namespace {
 struct Counters {
@@ -68,9 +80,13 @@ namespace {
 // Per-column parameters of the operator (e.g. one mass per column) that have
 // to follow the columns when the solver reorders them.
 struct ColParam {
-  std::vector<double> host;
+  std::vector<double> host;  // [ncol][stride]
   double* dev = nullptr;
   hipStream_t s = nullptr;
+  int stride = 1;
+  void swap(int a, int c) {
+    for (int k = 0; k < stride; ++k) std::swap(host[(size_t)a * stride + k], host[(size_t)c * stride + k]);
+  }
   int upload() const {
     return hipMemcpyAsync(dev, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice, s) == hipSuccess
                ? 0
@@ -100,7 +116,7 @@ struct Compactor {
       if ((e = vec_swap_cols(*v, a, c))) return e;
     for (int k = 0; k < ST_STRIDE; ++k) std::swap(st.h(a, k), st.h(c, k));
     for (auto* arr : arrays) std::swap((*arr)[a], (*arr)[c]);
-    if (cp) std::swap(cp->host[a], cp->host[c]);
+    if (cp) cp->swap(a, c);
     swaps.emplace_back(a, c);
     return 0;
   }
@@ -121,7 +137,7 @@ struct Compactor {
     int e = 0;
     for (auto it = swaps.rbegin(); it != swaps.rend(); ++it) {
       if ((e = vec_swap_cols(x, it->first, it->second)) || (e = vec_swap_cols(b, it->first, it->second))) return e;
-      if (cp) std::swap(cp->host[it->first], cp->host[it->second]);
+      if (cp) cp->swap(it->first, it->second);
     }
     if (cp && !swaps.empty() && (e = cp->upload())) return e;
     swaps.clear();
@@ -260,6 +276,12 @@ int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int pl
           st.h(c, ST_ACTIVE) = 0.0;
           st.h(c, ST_BETA) = 0.0;
         }
+      }
+      if (verbose()) {
+        double wr = 0.0;
+        for (int c = 0; c < na; ++c) wr = std::max(wr, bb[c] > 0 ? std::sqrt(st.h(c, ST_RR) / bb[c]) : 0.0);
+        fprintf(stderr, "[lq] cg iter %d: reliable update %d, %d active columns, worst rel. residual %.3e\n",
+                cnt.iters + it + 1, cnt.reliable, na, wr);
       }
       if ((e = compact())) return e;
     }
@@ -426,6 +448,337 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
 
 }  // namespace
 
+// ------------------------------------------------------------------ overlap
+// Overlap propagators through the chirally projected normal equations
+// (sec. 2.3).  With D = rho (1 + g5 eps) and eps^2 = 1, D is normal and
+//   D^dag D = rho^2 (2 + g5 eps + eps g5)
+// commutes with g5; on a vector of chirality s (g5 v = s v) it equals
+// 2 rho^2 (v + s P_s eps v), P_s = (1 + s g5)/2: one sign function per
+// application, and the result stays in the sector.  The massive operator
+// D(m) = (1 - m/(2 rho)) D + m satisfies
+//   D(m)^dag D(m) = (1 - m^2/(4 rho^2)) (H_s + sigma(m)),
+//   H_s = D^dag D on the sector, sigma(m) = m^2 / (1 - m^2/(4 rho^2)),
+// so all masses are shifts of one operator (multi-shift CG), and
+// x(m) = D(m)^dag z(m) with D(m)^dag D(m) z(m) = b (normality).  A source is
+// split into its two chiral halves; a point source has one.  With the
+// polynomial sign function eps_N^2 differs from 1 by the approximation error,
+// so the sector solve is wrapped in defect correction: the FP64 residual
+// b - D(m) x is recomputed with the full operator and solved for again
+// (both chiralities) until it meets the target.
+namespace {
+
+struct SecCol {
+  int i, j, s;  // mass index (ascending order), source column, chirality
+};
+
+// p coefficients of OP_PLC for the operators used below
+void plc_sector(double* q, double rho, double m, int s) {  // (1 - m^2/4rho^2)(H_s) + m^2
+  const double f = 1.0 - m * m / (4.0 * rho * rho);
+  q[0] = f * 2.0 * rho * rho + m * m;
+  q[1] = f * rho * rho;
+  q[2] = s;
+  q[3] = 1.0;
+}
+void plc_shifted(double* q, double rho, double sigma, int s) {  // H_s + sigma
+  q[0] = 2.0 * rho * rho + sigma;
+  q[1] = rho * rho;
+  q[2] = s;
+  q[3] = 1.0;
+}
+
+}  // namespace
+
+static int overlap_solve(OpEnv& env, const lq_params* prm, int n_rhs, const double* b_dev, double* x_dev,
+                         double tol, int maxiter, double delta, int plo, Counters& cnt, double& worst, int& status) {
+  lq_ctx* c = env.ctx;
+  const Geom& g = env.f->g;
+  hipStream_t s = env.s;
+  const double rho = env.act.rho;
+  int e = 0;
+  if ((e = overlap_prepare(env))) return e;
+  const int nm = prm->n_shift > 1 ? prm->n_shift : 1;
+  std::vector<double> mass_in(nm, env.act.m);
+  if (prm->n_shift > 1) {
+    if (!prm->masses) return fail(LQ_EINVAL, "overlap multi-mass solve needs masses");
+    mass_in.assign(prm->masses, prm->masses + nm);
+  }
+  for (double m : mass_in)
+    if (!(m > 0) || !(m < 2 * rho)) return fail(LQ_EINVAL, "overlap masses must lie in (0, 2 rho)");
+  if (prm->use_initial_guess && nm > 1) return fail(LQ_EINVAL, "overlap: initial guess with one mass only");
+  // internal order: ascending mass (ascending sigma), so the base shift comes first
+  std::vector<int> order(nm);
+  for (int i = 0; i < nm; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return mass_in[a] < mass_in[b2]; });
+  std::vector<double> mass(nm);
+  for (int i = 0; i < nm; ++i) mass[i] = mass_in[order[i]];
+  const int nx = nm * n_rhs;  // solution columns, mass-major
+
+  Vec b = make_vec(g, 64, 12, n_rhs, 2, 0, s);
+  Vec brep = make_vec(g, 64, 12, nx, 2, 0, s);
+  Vec x = make_vec(g, 64, 12, nx, 2, 0, s);
+  Vec r = make_vec(g, 64, 12, nx, 2, 0, s);
+  Vec t1 = make_vec(g, 64, 12, nx, 2, 0, s);
+  Vec t2 = make_vec(g, 64, 12, nx, 2, 0, s);
+  DBuf pxd(sizeof(double) * 4 * nx, s), pxdag(sizeof(double) * 4 * nx, s);
+  if (!b.ok() || !brep.ok() || !x.ok() || !r.ok() || !t1.ok() || !t2.ok() || !pxd.p || !pxdag.p)
+    return fail(LQ_ENOMEM, "overlap solution buffers");
+  if (launch_pack_field(g, b_dev, n_rhs, 12, b.f, 64, 2, s)) return fail(LQ_EDEVICE, "pack");
+  for (int i = 0; i < nm; ++i)
+    if (launch_convert(brep.cols(i * n_rhs), 64, b.f, 64, 12, n_rhs, 2, g.Vh, s)) return fail(LQ_EDEVICE, "copy");
+  if (prm->use_initial_guess) {
+    if (launch_pack_field(g, x_dev, n_rhs, 12, x.f, 64, 2, s)) return fail(LQ_EDEVICE, "pack");
+  } else if ((e = vec_zero(x))) return e;
+  // D(m) v = (rho + m/2) v + (rho - m/2) g5 eps v ; D(m)^dag v = (rho + m/2) v + (rho - m/2) eps g5 v
+  {
+    std::vector<double> hd((size_t)4 * nx), hdag((size_t)4 * nx);
+    for (int i = 0; i < nm; ++i)
+      for (int j = 0; j < n_rhs; ++j) {
+        double* q = &hd[(size_t)4 * (i * n_rhs + j)];
+        double* qd = &hdag[(size_t)4 * (i * n_rhs + j)];
+        q[0] = qd[0] = rho + 0.5 * mass[i];
+        q[1] = qd[1] = rho - 0.5 * mass[i];
+        q[2] = 0.0; q[3] = 1.0;
+        qd[2] = 1.0; qd[3] = 0.0;
+      }
+    hipMemcpyAsync(pxd.p, hd.data(), sizeof(double) * hd.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(pxdag.p, hdag.data(), sizeof(double) * hdag.size(), hipMemcpyHostToDevice, s);
+  }
+  Blas bl;
+  if ((e = blas_prepare(c, bl, g, 2, 2 * nx, s))) return e;
+  std::vector<double> bb;
+  if ((e = col_norms(bl, b, bb))) return e;
+
+  // r = brep - D(m) x on every solution column; res = |r| / |b|
+  std::vector<double> res(nx, 1.0);
+  auto residual = [&]() -> int {
+    int rr = 0;
+    if ((rr = sign_apply(env, 64, t1, x))) return rr;
+    if ((rr = bl.plc(&x, &t1, &r, pxd.as<double>()))) return rr;
+    if ((rr = bl.op(OP_XMY_NORM, &brep, &r))) return rr;  // r = brep - D x
+    State st(nx, s);
+    if (!st.ok()) return fail(LQ_ENOMEM, "state");
+    if (launch_scalar(SC_SET_RR, bl.partial, bl.gridx, nx, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if ((rr = st.pull())) return rr;
+    for (int k = 0; k < nx; ++k) {
+      const double bk = bb[k % n_rhs];
+      res[k] = bk > 0 ? std::sqrt(st.h(k, ST_RR) / bk) : 0.0;
+      if (!std::isfinite(res[k])) return fail(LQ_ENUMERIC, "NaN/Inf in the overlap residual");
+    }
+    return 0;
+  };
+
+  const int pms = plo == 16 ? 32 : plo;  // precision of the multi-shift stage
+  bool have_r = false;                   // r holds the residual of x
+  if (prm->use_initial_guess) {
+    if ((e = residual())) return e;
+    have_r = true;
+  }
+  worst = 1.0;
+  status = LQ_OK;
+  for (int pass = 0; pass < 8; ++pass) {
+    if (have_r) {
+      worst = *std::max_element(res.begin(), res.end());
+      if (worst <= tol) break;
+    }
+    // chiral sector sources: pass 0 from b (shared by the masses), later passes
+    // from the residual of each unconverged (mass, column)
+    std::vector<double> nrm;
+    Vec src = make_vec(g, 64, 12, have_r ? nx : n_rhs, 2, 0, s);
+    if (!src.ok()) return fail(LQ_ENOMEM, "overlap sector buffers");
+    if ((e = vec_copy(src, have_r ? r : b))) return e;
+    std::vector<SecCol> cols;
+    {
+      Vec halves = make_vec(g, 64, 12, 2 * src.ncol, 2, 0, s);
+      DBuf pp(sizeof(double) * 8 * src.ncol, s);
+      if (!halves.ok() || !pp.p) return fail(LQ_ENOMEM, "overlap sector buffers");
+      std::vector<double> hp((size_t)8 * src.ncol);
+      for (int k = 0; k < 2 * src.ncol; ++k) {
+        const int sg = (k & 1) ? -1 : 1;
+        double* q = &hp[(size_t)4 * k];
+        q[0] = 0.0; q[1] = 0.5; q[2] = 1.0; q[3] = sg;  // P_s v = (v + s g5 v) / 2
+        if (launch_convert(halves.cols(k), 64, src.cols(k / 2), 64, 12, 1, 2, g.Vh, s)) return fail(LQ_EDEVICE, "copy");
+      }
+      hipMemcpyAsync(pp.p, hp.data(), sizeof(double) * hp.size(), hipMemcpyHostToDevice, s);
+      if ((e = bl.plc(&halves, &halves, &halves, pp.as<double>()))) return e;
+      if ((e = col_norms(bl, halves, nrm))) return e;
+      // keep the nonzero halves (of unconverged columns)
+      std::vector<int> keep;
+      for (int k = 0; k < 2 * src.ncol; ++k) {
+        const int sc = k / 2;
+        if (have_r && res[sc] <= tol) continue;
+        if (!(nrm[k] > 0)) continue;
+        keep.push_back(k);
+      }
+      if (!have_r) {
+        // pass 0: the same sector sources for every mass, mass-major
+        for (int i = 0; i < nm; ++i)
+          for (int k : keep) cols.push_back(SecCol{i, k / 2, (k & 1) ? -1 : 1});
+      } else {
+        for (int k : keep) cols.push_back(SecCol{(k / 2) / n_rhs, (k / 2) % n_rhs, (k & 1) ? -1 : 1});
+      }
+      const int ncs = (int)cols.size();
+      if (ncs == 0) {
+        if (!have_r) {  // b = 0: x = 0
+          worst = 0.0;
+          std::fill(res.begin(), res.end(), 0.0);
+          break;
+        }
+        break;
+      }
+      src = make_vec(g, 64, 12, ncs, 2, 0, s);
+      if (!src.ok()) return fail(LQ_ENOMEM, "overlap sector buffers");
+      const int nkeep = (int)keep.size();
+      for (int q = 0; q < ncs; ++q) {
+        const int k = have_r ? keep[q] : keep[q % nkeep];
+        if (launch_convert(src.cols(q), 64, halves.cols(k), 64, 12, 1, 2, g.Vh, s)) return fail(LQ_EDEVICE, "copy");
+      }
+    }
+    const int ncs = src.ncol;
+    Vec z = make_vec(g, 64, 12, ncs, 2, 0, s);
+    if (!z.ok()) return fail(LQ_ENOMEM, "overlap sector buffers");
+    if ((e = vec_zero(z))) return e;
+    ColParam cp;
+    cp.stride = 4;
+    cp.s = s;
+    cp.host.assign((size_t)4 * ncs, 0.0);
+    for (int q = 0; q < ncs; ++q) plc_sector(&cp.host[(size_t)4 * q], rho, mass[cols[q].i], cols[q].s);
+    DBuf dcp(sizeof(double) * cp.host.size(), s);
+    if (!dcp.p) return fail(LQ_ENOMEM, "overlap parameters");
+    cp.dev = dcp.as<double>();
+    if ((e = cp.upload())) return e;
+
+    if (!have_r && nm > 1) {
+      // multi-shift CG on H_s + sigma_i (sloppy, no reliable updates), base = lightest mass
+      const int nsec = ncs / nm;
+      std::vector<double> sig(nm);
+      for (int i = 0; i < nm; ++i) sig[i] = mass[i] * mass[i] / (1.0 - mass[i] * mass[i] / (4.0 * rho * rho));
+      std::vector<double> dsh(nm);
+      for (int i = 0; i < nm; ++i) dsh[i] = sig[i] - sig[0];
+      DBuf dsig(sizeof(double) * nm, s), pbase(sizeof(double) * 4 * nsec, s);
+      Vec rr = make_vec(g, pms, 12, nsec, 2, 0, s), ap = make_vec(g, pms, 12, nsec, 2, 0, s),
+          ee = make_vec(g, pms, 12, nsec, 2, 0, s), p = make_vec(g, pms, 12, ncs, 2, 0, s),
+          xm = make_vec(g, pms, 12, ncs, 2, 0, s);
+      State st(nsec, s);
+      DBuf sh(sizeof(double) * 8 * ncs, s);
+      if (!dsig.p || !pbase.p || !rr.ok() || !ap.ok() || !ee.ok() || !p.ok() || !xm.ok() || !st.ok() || !sh.p)
+        return fail(LQ_ENOMEM, "overlap multi-shift buffers");
+      hipMemcpyAsync(dsig.p, dsh.data(), sizeof(double) * nm, hipMemcpyHostToDevice, s);
+      {
+        std::vector<double> hb((size_t)4 * nsec);
+        for (int q = 0; q < nsec; ++q) plc_shifted(&hb[(size_t)4 * q], rho, sig[0], cols[q].s);
+        hipMemcpyAsync(pbase.p, hb.data(), sizeof(double) * hb.size(), hipMemcpyHostToDevice, s);
+      }
+      Vec src0 = view(src, 0, nsec);
+      if (vec_copy(rr, src0) || vec_zero(xm)) return fail(LQ_EDEVICE, "init");
+      for (int i = 0; i < nm; ++i)
+        if (launch_convert(p.cols(i * nsec), pms, src0.f, 64, 12, nsec, 2, g.Vh, s)) return fail(LQ_EDEVICE, "copy");
+      const double tol_ms = std::max(tol, pms == 32 ? 1e-6 : pms == 16 ? 2e-3 : tol);
+      for (int j = 0; j < nsec; ++j) {
+        for (int k = 0; k < ST_STRIDE; ++k) st.h(j, k) = 0.0;
+        st.h(j, ST_ACTIVE) = 1.0;
+        st.h(j, ST_PAD) = tol_ms * tol_ms;
+      }
+      if ((e = st.push())) return e;
+      Blas blr;
+      if ((e = blas_prepare(c, blr, g, 2, ncs, s))) return e;
+      MsArgs M{};
+      M.prec = pms; M.nc = 12; M.nrhs = nsec; M.nshift = nm; M.npar = 2; M.Vh = g.Vh;
+      M.x = xm.f; M.p = p.f; M.r = rr.f; M.ap = ap.f;
+      M.sh = sh.as<double>(); M.st = st.d(); M.partial = blr.partial; M.gridx = blr.gridx;
+      if ((e = blr.op(OP_NORM2, &rr))) return e;
+      if (launch_ms_init(M, s)) return fail(LQ_EDEVICE, "ms init");
+      std::vector<double> hsh((size_t)8 * ncs);
+      Vec p0 = view(p, 0, nsec);
+      int it = 0;
+      for (; it < maxiter; ++it) {
+        if ((e = sign_apply(env, pms, ee, p0))) return e;
+        if ((e = blr.plc(&p0, &ee, &ap, pbase.as<double>()))) return e;
+        if ((e = blr.op(OP_DOT, &p0, &ap))) return e;
+        if (launch_ms_scalar_alpha(M, dsig.as<double>(), s)) return fail(LQ_EDEVICE, "ms alpha");
+        {
+          Prof pr(c, "blas", s);
+          if (launch_ms_xr(M, s)) return fail(LQ_EDEVICE, "ms xr");
+        }
+        if (launch_ms_scalar_beta(M, s)) return fail(LQ_EDEVICE, "ms beta");
+        {
+          Prof pr(c, "blas", s);
+          if (launch_ms_p(M, s)) return fail(LQ_EDEVICE, "ms p");
+        }
+        hipMemcpyAsync(hsh.data(), sh.p, sizeof(double) * 8 * ncs, hipMemcpyDeviceToHost, s);
+        if ((e = st.pull())) return e;
+        bool any = false;
+        for (int k = 0; k < ncs; ++k) any |= hsh[(size_t)k * 8 + 4] != 0.0;
+        for (int j = 0; j < nsec; ++j)
+          if (st.h(j, ST_FLAG) == 2.0) return fail(LQ_ENUMERIC, "NaN/Inf in multi-shift CG");
+        if (!any) break;
+      }
+      cnt.iters += it;
+      // z_i = (H_s + sigma_i)^{-1} src / (1 - m_i^2 / (4 rho^2))
+      if ((e = vec_copy(z, xm))) return e;
+      for (int i = 0; i < nm; ++i) {
+        Vec zi = view(z, i * nsec, nsec);
+        if ((e = bl.opi(OP_SCALE, &zi, nullptr, nullptr, 1.0 / (1.0 - mass[i] * mass[i] / (4.0 * rho * rho)))))
+          return e;
+      }
+    }
+
+    // sector solve with FP64 reliable updates (the sector operator per column)
+    Vec e64 = make_vec(g, 64, 12, ncs, 2, 0, s), elo = make_vec(g, plo, 12, ncs, 2, 0, s);
+    if (!e64.ok() || !elo.ok()) return fail(LQ_ENOMEM, "overlap sector buffers");
+    Blas bls;
+    if ((e = blas_prepare(c, bls, g, 2, ncs, s))) return e;
+    OpFn Ahi = [&](Vec& o, const Vec& in) {
+      Vec t = view(e64, 0, in.ncol);
+      int rr = sign_apply(env, 64, t, in);
+      return rr ? rr : bls.plc(const_cast<Vec*>(&in), &t, &o, cp.dev);
+    };
+    OpFn Alo = [&](Vec& o, const Vec& in) {
+      Vec t = view(elo, 0, in.ncol);
+      int rr = sign_apply(env, plo, t, in);
+      return rr ? rr : bls.plc(const_cast<Vec*>(&in), &t, &o, cp.dev);
+    };
+    // |r_ij - D D^dag z| <= tol |b_j| from per-sector targets relative to each sector source
+    std::vector<double> tolv(ncs);
+    {
+      std::vector<double> sn;
+      if ((e = col_norms(bl, src, sn))) return e;
+      for (int q = 0; q < ncs; ++q) {
+        const double bj = std::sqrt(bb[cols[q].j]), sq = std::sqrt(sn[q]);
+        tolv[q] = sq > 0 ? std::min(0.1, 0.25 * tol * bj / sq) : 1.0;
+      }
+    }
+    const int rs = cg_mixed(bls, g, Ahi, Alo, plo, z, src, tolv, maxiter, delta, cnt, &cp);
+    if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
+    status = rs;
+    // y_ij = sum of the sector solutions ; x_ij += D(m_i)^dag y_ij
+    if ((e = vec_zero(t2))) return e;
+    for (int q = 0; q < ncs; ++q) {
+      const int col = cols[q].i * n_rhs + cols[q].j;
+      Vec zq = view(z, q, 1), yq = view(t2, col, 1);
+      if ((e = bl.opi(OP_AXPY, &zq, &yq, nullptr, 1.0))) return e;
+    }
+    if ((e = bl.op(OP_G5, &t2, &r))) return e;
+    if ((e = sign_apply(env, 64, t1, r))) return e;
+    if ((e = bl.plc(&t2, &t1, &r, pxdag.as<double>()))) return e;
+    if ((e = bl.opi(OP_AXPY, &r, &x, nullptr, 1.0))) return e;
+    if ((e = residual())) return e;
+    have_r = true;
+    worst = *std::max_element(res.begin(), res.end());
+    if (verbose())
+      fprintf(stderr, "[lq] overlap pass %d: %d sector columns, worst rel. residual of D(m) x = b %.3e\n", pass, ncs,
+              worst);
+    if (worst <= tol || rs == LQ_ENOCONV) break;
+  }
+  // output in the caller's mass order: x is [n_shift][n_rhs][V][4][3]
+  const size_t colsz = (size_t)2 * g.Vh * 12 * 2;
+  for (int i = 0; i < nm; ++i) {
+    Vec v = view(x, i * n_rhs, n_rhs);
+    if (launch_unpack_field(g, v.f, 64, n_rhs, 12, x_dev + (size_t)order[i] * n_rhs * colsz, 2, s))
+      return fail(LQ_EDEVICE, "unpack");
+  }
+  return 0;
+}
+
 // ------------------------------------------------------------------ top-level solve
 int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, int n_rhs, const double* b_dev,
           double* x_dev, lq_stats* stats, hipStream_t s) {
@@ -447,7 +800,10 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
   int status = LQ_OK;
   const int kind = act->kind;
 
-  if (kind == LQ_WILSON || kind == LQ_TM_CLOVER || kind == LQ_OVERLAP) {
+  if (kind == LQ_OVERLAP && prm->solver != 1) {
+    if (f->type != 0) return fail(LQ_EINVAL, "field type does not match the action");
+    if ((e = overlap_solve(env, prm, n_rhs, b_dev, x_dev, tol, maxiter, delta, plo, cnt, worst, status))) return e;
+  } else if (kind == LQ_WILSON || kind == LQ_TM_CLOVER || kind == LQ_OVERLAP) {
     if (kind == LQ_TM_CLOVER && plo == 16) return fail(LQ_ENOTSUP, "twisted-clover sloppy storage is FP32 or FP64");
     if (kind == LQ_OVERLAP && (e = overlap_prepare(env))) return e;
     Vec b = make_vec(g, 64, 12, n_rhs, 2, 0, s);
@@ -821,8 +1177,80 @@ static void tridiag_extremes(const std::vector<double>& a, const std::vector<dou
   hi = kth(n - 1);
 }
 
-int hw_bounds(lq_ctx* c, const lq_action* act, lq_field* f, int iters, double* lmin, double* lmax, hipStream_t s) {
+// Solves (T - mu) y = y in place for the symmetric tridiagonal T (diagonal a,
+// off-diagonal b) by Gaussian elimination with partial pivoting; the factor
+// of a tridiagonal matrix then has two super-diagonals.
+static void tri_shift_solve(const std::vector<double>& a, const std::vector<double>& b, double mu,
+                            std::vector<double>& y) {
+  const int n = (int)a.size();
+  std::vector<double> d(n), du(n, 0.0), du2(n, 0.0), dl(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = a[i] - mu;
+  for (int i = 0; i + 1 < n; ++i) du[i] = dl[i] = b[i];
+  std::vector<char> piv(n, 0);
+  for (int i = 0; i + 1 < n; ++i) {
+    if (std::fabs(d[i]) >= std::fabs(dl[i])) {
+      const double f = d[i] != 0.0 ? dl[i] / d[i] : 0.0;
+      dl[i] = f;
+      d[i + 1] -= f * du[i];
+    } else {
+      // exchange rows i and i+1
+      const double f = d[i] / dl[i];
+      d[i] = dl[i];
+      dl[i] = f;
+      const double t = du[i];
+      du[i] = d[i + 1];
+      d[i + 1] = t - f * d[i + 1];
+      if (i + 2 < n) {
+        du2[i] = du[i + 1];
+        du[i + 1] = -f * du[i + 1];
+      }
+      piv[i] = 1;
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    if (d[i] == 0.0) d[i] = 1e-300;
+  for (int i = 0; i + 1 < n; ++i) {
+    if (piv[i]) std::swap(y[i], y[i + 1]);
+    y[i + 1] -= dl[i] * y[i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double v = y[i];
+    if (i + 1 < n) v -= du[i] * y[i + 1];
+    if (i + 2 < n) v -= du2[i] * y[i + 2];
+    y[i] = v / d[i];
+  }
+}
+
+// unit eigenvector of T for the eigenvalue theta by inverse iteration
+static std::vector<double> tri_eigvec(const std::vector<double>& a, const std::vector<double>& b, double theta) {
+  const int n = (int)a.size();
+  std::vector<double> y(n, 1.0 / std::sqrt((double)std::max(n, 1)));
+  const double mu = theta + 1e-13 * std::max(1.0, std::fabs(theta));
+  for (int it = 0; it < 4; ++it) {
+    tri_shift_solve(a, b, mu, y);
+    double nn = 0.0;
+    for (double v : y) nn += v * v;
+    nn = std::sqrt(nn);
+    if (!(nn > 0) || !std::isfinite(nn)) break;
+    for (double& v : y) v /= nn;
+  }
+  return y;
+}
+
+// Interval of the spectrum of H_W^2 (sec. 2.3: the Chebyshev interval must
+// hold it).  FP64 Lanczos from a fixed random start vector gives the
+// tridiagonal T; Sturm bisection gives its extreme eigenvalues theta_min and
+// theta_max, inverse iteration their eigenvectors s.  A second Lanczos pass
+// (deterministic reductions reproduce the same basis vectors v_j bit for bit)
+// forms the Ritz vectors y = sum_j s_j v_j, and their residuals
+// r = |H^2 y - theta y| / |y| are computed with the FP64 operator.  Some
+// eigenvalue lies within r of each Ritz value, and Lanczos from a random
+// start approaches the extreme eigenvalues from inside the spectrum, so
+// [theta_min - r_min, theta_max + r_max] is taken to hold the spectrum.
+// Lanczos counts as converged when r_min < theta_min / 2; otherwise LQ_EINVAL.
+int hw_spectrum(lq_ctx* c, const lq_action* act, lq_field* f, int iters, HwSpectrum* out, hipStream_t s) {
   if (f->type != 0) return fail(LQ_EINVAL, "H_W bounds need a Wilson gauge field");
+  if (iters < 2) return fail(LQ_EINVAL, "H_W bounds need at least 2 Lanczos steps");
   const Geom& g = f->g;
   OpEnv env{c, f, *act, s};
   Blas bl;
@@ -835,41 +1263,94 @@ int hw_bounds(lq_ctx* c, const lq_action* act, lq_field* f, int iters, double* l
   for (auto& v : h) v = nd01(rng);
   DBuf raw(sizeof(double) * nd, s);
   Vec v = make_vec(g, 64, 12, 1, 2, 0, s), w = make_vec(g, 64, 12, 1, 2, 0, s),
-      vp = make_vec(g, 64, 12, 1, 2, 0, s), t = make_vec(g, 64, 12, 1, 2, 0, s);
-  if (!raw.p || !v.ok() || !w.ok() || !vp.ok() || !t.ok()) return fail(LQ_ENOMEM, "lanczos buffers");
+      vp = make_vec(g, 64, 12, 1, 2, 0, s), t = make_vec(g, 64, 12, 1, 2, 0, s),
+      ylo = make_vec(g, 64, 12, 1, 2, 0, s), yhi = make_vec(g, 64, 12, 1, 2, 0, s);
+  if (!raw.p || !v.ok() || !w.ok() || !vp.ok() || !t.ok() || !ylo.ok() || !yhi.ok())
+    return fail(LQ_ENOMEM, "lanczos buffers");
   hipMemcpyAsync(raw.p, h.data(), sizeof(double) * nd, hipMemcpyHostToDevice, s);
-  if (launch_pack_field(g, raw.as<double>(), 1, 12, v.f, 64, 2, s)) return fail(LQ_EDEVICE, "pack");
-  std::vector<double> nn;
-  if ((e = col_norms(bl, v, nn))) return e;
-  if ((e = bl.opi(OP_SCALE, &v, nullptr, nullptr, 1.0 / std::sqrt(nn[0])))) return e;
-  if ((e = vec_zero(vp))) return e;
-  std::vector<double> al, be;
-  double beta_prev = 0.0;
   State st(1, s);
-  for (int j = 0; j < iters; ++j) {
-    if ((e = hw_apply(env, 64, t, v)) || (e = hw_apply(env, 64, w, t))) return e;  // w = H^2 v
-    if ((e = bl.op(OP_DOT, &v, &w))) return e;
-    if (launch_scalar(SC_DOT_TO_AUX, bl.partial, bl.gridx, 1, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
-    if ((e = st.pull())) return e;
-    const double alpha = st.h(0, ST_AUX);
-    al.push_back(alpha);
-    // w = w - alpha v - beta_prev vp
-    if ((e = bl.opi(OP_AXMY, &v, &w, nullptr, alpha))) return e;
-    if ((e = bl.opi(OP_AXMY, &vp, &w, nullptr, beta_prev))) return e;
-    if ((e = col_norms(bl, w, nn))) return e;
-    const double beta = std::sqrt(nn[0]);
-    if (!(beta > 1e-14) || j == iters - 1) break;
-    be.push_back(beta);
-    std::swap(vp, v);
-    if ((e = bl.opi(OP_SCALE, &w, nullptr, nullptr, 1.0 / beta))) return e;
-    std::swap(v, w);
-    beta_prev = beta;
-  }
-  be.resize(al.size() > 0 ? al.size() - 1 : 0);
+  if (!st.ok()) return fail(LQ_ENOMEM, "lanczos state");
+  std::vector<double> al, be;
+  double beta_last = 0.0;
+  // one Lanczos run; visit(j) sees the normalised basis vector v_j in v
+  auto lanczos = [&](int m, const std::function<int(int)>& visit) -> int {
+    int r = 0;
+    al.clear();
+    be.clear();
+    if (launch_pack_field(g, raw.as<double>(), 1, 12, v.f, 64, 2, s)) return fail(LQ_EDEVICE, "pack");
+    std::vector<double> nn;
+    if ((r = col_norms(bl, v, nn))) return r;
+    if ((r = bl.opi(OP_SCALE, &v, nullptr, nullptr, 1.0 / std::sqrt(nn[0])))) return r;
+    if ((r = vec_zero(vp))) return r;
+    double beta_prev = 0.0;
+    for (int j = 0; j < m; ++j) {
+      if (visit && (r = visit(j))) return r;
+      if ((r = hw_apply(env, 64, t, v)) || (r = hw_apply(env, 64, w, t))) return r;  // w = H^2 v
+      if ((r = bl.op(OP_DOT, &v, &w))) return r;
+      if (launch_scalar(SC_DOT_TO_AUX, bl.partial, bl.gridx, 1, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+      if ((r = st.pull())) return r;
+      const double alpha = st.h(0, ST_AUX);
+      al.push_back(alpha);
+      // w = w - alpha v - beta_prev vp
+      if ((r = bl.opi(OP_AXMY, &v, &w, nullptr, alpha))) return r;
+      if ((r = bl.opi(OP_AXMY, &vp, &w, nullptr, beta_prev))) return r;
+      if ((r = col_norms(bl, w, nn))) return r;
+      const double beta = std::sqrt(nn[0]);
+      beta_last = beta;
+      if (!(beta > 1e-14 * std::fabs(alpha)) || j == m - 1) break;
+      be.push_back(beta);
+      std::swap(vp, v);
+      if ((r = bl.opi(OP_SCALE, &w, nullptr, nullptr, 1.0 / beta))) return r;
+      std::swap(v, w);
+      beta_prev = beta;
+    }
+    return 0;
+  };
+  if ((e = lanczos(iters, nullptr))) return e;
+  const int m = (int)al.size();
+  be.resize(m > 0 ? m - 1 : 0);
   double lo = 0, hi = 0;
   tridiag_extremes(al, be, lo, hi);
-  *lmin = std::sqrt(std::max(lo, 0.0));
-  *lmax = std::sqrt(std::max(hi, 0.0));
+  const std::vector<double> slo = tri_eigvec(al, be, lo), shi = tri_eigvec(al, be, hi);
+  const std::vector<double> a_keep = al, b_keep = be;
+  if ((e = vec_zero(ylo)) || (e = vec_zero(yhi))) return e;
+  e = lanczos(m, [&](int j) -> int {
+    int r = bl.opi(OP_AXPY, &v, &ylo, nullptr, slo[j]);
+    return r ? r : bl.opi(OP_AXPY, &v, &yhi, nullptr, shi[j]);
+  });
+  if (e) return e;
+  if (al != a_keep) return fail(LQ_EDEVICE, "lanczos: second pass did not reproduce the basis");
+  // r = |H^2 y - theta y| / |y|
+  auto ritz_res = [&](Vec& y, double theta, double& res) -> int {
+    int r = 0;
+    std::vector<double> ny, nq;
+    if ((r = col_norms(bl, y, ny))) return r;
+    if ((r = hw_apply(env, 64, t, y)) || (r = hw_apply(env, 64, w, t))) return r;
+    if ((r = bl.opi(OP_AXMY, &y, &w, nullptr, theta))) return r;
+    if ((r = col_norms(bl, w, nq))) return r;
+    res = ny[0] > 0 ? std::sqrt(nq[0] / ny[0]) : 1e300;
+    return 0;
+  };
+  double rlo = 0, rhi = 0;
+  if ((e = ritz_res(ylo, lo, rlo)) || (e = ritz_res(yhi, hi, rhi))) return e;
+  out->theta_min = lo;
+  out->theta_max = hi;
+  out->r_min = rlo;
+  out->r_max = rhi;
+  out->steps = m;
+  if (!(rlo < 0.5 * lo) || !std::isfinite(rhi))
+    return fail(LQ_EINVAL, "Lanczos on H_W^2 has not converged: Ritz residual " + std::to_string(rlo) +
+                               " of the smallest Ritz value " + std::to_string(lo) + " after " + std::to_string(m) +
+                               " steps");
+  return 0;
+}
+
+int hw_bounds(lq_ctx* c, const lq_action* act, lq_field* f, int iters, double* lmin, double* lmax, hipStream_t s) {
+  HwSpectrum sp{};
+  int e = hw_spectrum(c, act, f, iters, &sp, s);
+  if (e) return e;
+  *lmin = std::sqrt(std::max(sp.theta_min - sp.r_min, 0.0));
+  *lmax = std::sqrt(sp.theta_max + sp.r_max);
   return 0;
 }
 

@@ -241,7 +241,7 @@ def lq_apply(ctx, act, field, op, prec_bits, inp, out=None):
 def lq_solve(ctx, act, field, prm, b, x=None):
     """Solve D x = b for the columns of b; returns (x, stats dict).
 
-    For HISQ with several masses x has a leading n_shift axis.  A non-converged
+    For HISQ or overlap with several masses x has a leading n_shift axis.  A non-converged
     solve (LQ_ENOCONV) still returns x and stats with stats['status'] set.
     """
     n_rhs = b.shape[0]

@@ -182,7 +182,7 @@ def test_hw_and_sign(ctx, prec):
         assert rel(out, np.array([OV.hw(U, p, rho) for p in psi])) < TOL[prec]
         out = L.lq_apply(ctx, act, f, L.LQ_OP_SIGN, prec, psi)
         want = np.array([OV.sign_hw(U, p, rho, c, a, b) for p in psi])
-        tol = {64: 1e-12, 32: 2e-5, 16: 1e-2}[prec]
+        tol = {64: 1e-12, 32: 2e-5, 16: 3e-3}[prec]
         assert rel(out, want) < tol
         out = L.lq_apply(ctx, act, f, L.LQ_OP_D, prec, psi)
         want = np.array([OV.overlap(U, p, rho, 0.015, c, a, b) for p in psi])
@@ -198,8 +198,10 @@ def test_hw_bounds_contain_spectrum(ctx):
         act = L.action(L.LQ_OVERLAP, m=0.0, rho=1.5, cheb_N=10)
         lo, hi = L.lq_hw_bounds(ctx, act, f, 300)
         lo_o, hi_o = OV.hw_extremes(U, 1.5)
-        assert abs(hi - hi_o) < 1e-6 * hi_o
-        assert lo >= lo_o * (1 - 1e-6) and lo < 1.25 * lo_o
+        # certified: the interval holds the spectrum, and 0.9 lo^2 (the
+        # Chebyshev end the library takes) lies below the smallest eigenvalue
+        assert hi >= hi_o * (1 - 1e-9) and hi < 1.05 * hi_o
+        assert lo <= lo_o * (1 + 1e-9) and 0.9 * lo * lo <= lo_o * lo_o and lo > 0.7 * lo_o
     finally:
         L.lq_field_free(f)
 

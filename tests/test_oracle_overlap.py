@@ -127,3 +127,63 @@ def test_overlap_eigenvalues_on_circle_2x4():
     Dov = np.array(cols).T
     ev = np.linalg.eigvals(Dov)
     assert np.abs(np.abs(ev - RHO) - RHO).max() < 10 * delta + 1e-10
+
+
+def test_hw_extremes_matches_dense_spectrum_2x4():
+    """The oracle's ARPACK interval equals the extreme |eigenvalues| of the
+    dense H_W at 2^4 (numpy eigvalsh), so it can serve as the checker of the
+    library's Lanczos interval."""
+    L = (2, 2, 2, 2)
+    for seed in (231, 232):
+        U = synth.su3_field(L, 0.3, seed)
+        H = _dense_hw(U)
+        w = np.linalg.eigvalsh(H @ H)
+        lo, hi = OV.hw_extremes(U, RHO)
+        assert abs(lo - np.sqrt(w[0])) < 1e-8 * np.sqrt(w[0])
+        assert abs(hi - np.sqrt(w[-1])) < 1e-8 * np.sqrt(w[-1])
+
+
+def test_chiral_normal_operator_identity_2x4():
+    """The identity behind the chirally projected overlap solve (sec. 2.3):
+    with the exact sign function, on a vector of chirality s,
+    D(m)^dag D(m) v = (1 - m^2/(4 rho^2)) 2 rho^2 (v + s P_s eps v) + m^2 v,
+    and D(m) is normal.  Checked on the dense operator at 2^4."""
+    L = (2, 2, 2, 2)
+    U = synth.su3_field(L, 0.3, 241)
+    H = _dense_hw(U)
+    w, Q = np.linalg.eigh(H)
+    eps = (Q * np.sign(w)) @ Q.conj().T
+    n = H.shape[0]
+    g5 = np.kron(np.eye(n // 12), np.kron(lat.GAMMA5, np.eye(3)))
+    for m in (0.015, 0.1):
+        D = (RHO - m / 2) * (np.eye(n) + g5 @ eps) + m * np.eye(n)
+        N = D.conj().T @ D
+        assert np.abs(N - D @ D.conj().T).max() < 1e-12
+        v = synth.gaussian_spinor(L, 1, 242)[0].ravel()
+        f = 1.0 - m * m / (4 * RHO * RHO)
+        for s in (1, -1):
+            P = 0.5 * (np.eye(n) + s * g5)
+            vs = P @ v
+            want = f * 2 * RHO ** 2 * (vs + s * P @ (eps @ vs)) + m * m * vs
+            assert np.abs(N @ vs - want).max() < 1e-12 * np.abs(want).max()
+            # the sector form as the solver evaluates it: p0 v + p1 (s e + g5 e), e = eps v
+            e = eps @ vs
+            alt = (f * 2 * RHO ** 2 + m * m) * vs + f * RHO ** 2 * (s * e + g5 @ e)
+            assert np.abs(alt - want).max() < 1e-12 * np.abs(want).max()
+        # masses are shifts of one operator: D(m)^dag D(m) = f (D(0)^dag D(0) + m^2 / f)
+        D0 = RHO * (np.eye(n) + g5 @ eps)
+        assert np.abs(N - f * (D0.conj().T @ D0 + m * m / f * np.eye(n))).max() < 1e-12
+
+
+def test_golden_hw_spectra_come_from_the_oracle():
+    """tests/golden/hw_spectra.json (the Chebyshev intervals of the GPU overlap
+    tests) holds what the oracle computes: the 4^4 entry is recomputed here."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hw_spectra.json")
+    with open(here) as f:
+        t = json.load(f)
+    e = t["4x4x4x4_eps0.2_seed311_rho1.5"]
+    U = synth.su3_field(tuple(e["L"]), e["eps"], e["seed"])
+    lo, hi = OV.hw_extremes(U, e["rho"], tol=1e-8)
+    assert abs(lo - e["lmin"]) < 1e-7 * lo and abs(hi - e["lmax"]) < 1e-7 * hi
