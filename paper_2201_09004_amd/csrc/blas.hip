@@ -280,6 +280,14 @@ __global__ void scalar_kernel(int op, const double* partial, int gridx, int ncol
       double b = rr / s[ST_RR];
       if (!isfinite(rr)) s[ST_FLAG] = 2;
       if (!isfinite(b)) b = 0;
+      if (s[ST_FLAG] == 1) {
+        // the column took no step (SC_CG_ALPHA lost positivity): restart its
+        // direction with p = r, here on the device, so that iterations whose
+        // state the host does not read restart as well
+        b = 0;
+        s[ST_FLAG] = 0;
+        s[ST_NRST] += 1;
+      }
       setc(ST_BETA, {active ? b : 0.0, 0.0});
       s[ST_RR] = rr;
       break;

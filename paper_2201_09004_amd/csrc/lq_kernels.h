@@ -99,8 +99,9 @@ enum {
 };
 
 constexpr int ST_STRIDE = 16;  // doubles of solver state per column
+// ST_NRST: CG direction restarts after a loss of positivity of <p, A p>
 enum { ST_RHO = 0, ST_ALPHA = 2, ST_OMEGA = 4, ST_BETA = 6, ST_RR = 8, ST_FLAG = 9, ST_ACTIVE = 10, ST_AUX = 11,
-       ST_RR0 = 13, ST_PAD = 14 };
+       ST_RR0 = 13, ST_PAD = 14, ST_NRST = 15 };
 
 struct BlasArgs {
   int prec, nc, ncol, npar, Vh, op;

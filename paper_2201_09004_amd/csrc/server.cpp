@@ -410,12 +410,12 @@ class HisqEngine : public Engine {
     if (hipStreamSynchronize(s) != hipSuccess) return fail(LQ_EDEVICE, "engine step");
     last_used = Clock::now();
     UpdateRule rule;
-    std::vector<int> restart;  // columns that took no step (alpha = 0): p = r next
+    // (a column that lost positivity of <p, A p> took no step; SC_CG_BETA
+    // restarted its direction on the device)
     for (int c = 0; c < w; ++c) {
       ColMeta& m = cols[c];
       ++m.iters;
       if (st.h(c, ST_FLAG) == 2.0 || !std::isfinite(st.h(c, ST_RR))) return fail(LQ_ENUMERIC, "NaN/Inf residual");
-      if (st.h(c, ST_FLAG) == 1.0) restart.push_back(c);
       const double rr = st.h(c, ST_RR);
       m.maxrr = std::max(m.maxrr, rr);
       rule.column(rr, m.maxrr, m.tol * m.tol * m.bb, delta);
@@ -439,13 +439,6 @@ class HisqEngine : public Engine {
         m.maxrr = st.h(c, ST_RR);
         if (st.h(c, ST_RR) <= m.tol * m.tol * m.bb || m.iters >= maxiter) finished.push_back(c);
       }
-    }
-    if (!restart.empty()) {
-      for (int c : restart) {
-        st.h(c, ST_FLAG) = 0.0;
-        st.h(c, ST_BETA) = 0.0;
-      }
-      if ((e = st.push(w))) return e;
     }
     if ((e = ble.op(OP_XPAY, &rv, &pv, nullptr, nullptr, nullptr, st.d(), ST_BETA, ST_BETA))) return e;
     std::sort(finished.rbegin(), finished.rend());

@@ -202,9 +202,9 @@ int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int pl
   if ((e = compact())) return e;
   bool dirty = false;  // xs holds un-folded updates
   // Host checks of the residual norms may be deferred while every column is
-  // predicted to be far from its next update-rule threshold (not with FP16
-  // sloppy vectors, whose positivity restarts are set by the host).
-  const bool defer = plo != 16 && cnt.fault == 0;
+  // predicted to be far from its next update-rule threshold (positivity
+  // restarts happen on the device, so FP16 sloppy vectors defer as well).
+  const bool defer = cnt.fault == 0;
   int skip = 0, since = 0;
   int it = 0;
   for (; it < maxiter && na > 0; ++it) {
@@ -230,23 +230,17 @@ int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int pl
     dirty = true;
     if ((e = st.pull(na))) return e;
     UpdateRule rule;
-    std::vector<int> restart;  // columns that took no step (alpha = 0): p = r next
+    double nrst = 0.0;  // direction restarts (taken on the device by SC_CG_BETA)
     for (int c = 0; c < na; ++c) {
       if (st.h(c, ST_FLAG) == 2.0) return fail(LQ_ENUMERIC, "NaN/Inf in a CG reduction");
-      if (st.h(c, ST_FLAG) == 1.0) {
-        if (++cnt.restarts > 50 * n) return fail(LQ_EBREAKDOWN, "CG keeps losing positivity of <p, A p>");
-        restart.push_back(c);
-      }
+      nrst += st.h(c, ST_NRST);
       const double rr = st.h(c, ST_RR);
       maxrr[c] = std::max(maxrr[c], rr);
       rule.column(rr, maxrr[c], tol[c] * tol[c] * bb[c], delta);
     }
+    for (int c = na; c < n; ++c) nrst += st.h(c, ST_NRST);
+    if (nrst > 50.0 * n) return fail(LQ_EBREAKDOWN, "CG keeps losing positivity of <p, A p>");
     const bool update = rule.fire();
-    for (int c : restart) {
-      st.h(c, ST_FLAG) = 0.0;
-      st.h(c, ST_BETA) = 0.0;
-    }
-    if (!restart.empty() && (e = st.push(na))) return e;
     if (defer && !update) {
       double k = 8.0;
       for (int c = 0; c < na; ++c)
@@ -329,10 +323,10 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
   std::vector<double> bb, tol(tol_in);
   int e = col_norms(bl, b, bb);
   if (e) return e;
-  std::vector<double> maxrr(n);
+  std::vector<double> maxrr(n), rr_chk(n);  // rr_chk: |r|^2 at the last host check
   // active columns occupy slots [0, cm.na); v carries column data from one
   // iteration's M p into the same iteration's p update, across a compaction
-  Compactor cm{st, x, b, {&rs, &rhat, &p, &v, &xs}, {&bb, &tol, &maxrr}, nullptr, n, {}};
+  Compactor cm{st, x, b, {&rs, &rhat, &p, &v, &xs}, {&bb, &tol, &maxrr, &rr_chk}, nullptr, n, {}};
   auto V = [&](Vec& f) { return view(f, 0, cm.na); };
   auto true_res = [&]() -> int {
     Vec qv = V(q64), xv = V(x), bv = V(b);
@@ -361,12 +355,18 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
   if ((e = restart())) return e;
   if ((e = st.pull())) return e;
   for (int c = 0; c < n; ++c) {
-    maxrr[c] = st.h(c, ST_RR);
+    maxrr[c] = rr_chk[c] = st.h(c, ST_RR);
     const bool act = st.h(c, ST_RR) > tol[c] * tol[c] * bb[c] && bb[c] > 0;
     st.h(c, ST_ACTIVE) = act ? 1.0 : 0.0;
   }
   if ((e = cm.compact())) return e;
   bool dirty = false;
+  // Host reads of the state may be deferred, as in CG, while every column is
+  // predicted to be far from its next update-rule threshold.  A breakdown in a
+  // skipped iteration leaves its column frozen (zero steps, sticky flag) until
+  // the next read restarts it.
+  const bool defer = cnt.fault == 0;
+  int skip = 0, since = 0;
   int it = 0;
   for (; it < maxiter && cm.na > 0; ++it) {
     const int na = cm.na;
@@ -391,6 +391,12 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
     if ((e = bl.op(OP_BICG_XR, &pv, &rsv, &tv, &xsv, &rhv, st.d(), ST_ALPHA, ST_OMEGA))) return e;
     if (launch_scalar(SC_BICG_BETA, bl.partial, bl.gridx, na, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
     dirty = true;
+    ++since;
+    if (defer && skip > 0 && it < maxiter - 1) {
+      --skip;
+      if ((e = bl.op(OP_BICG_P, &rsv, &vv, &pv, nullptr, nullptr, st.d(), ST_BETA, ST_OMEGA))) return e;
+      continue;
+    }
     if ((e = st.pull(na))) return e;
     bool breakdown = false;
     UpdateRule rule;
@@ -403,6 +409,15 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
       rule.column(rr, maxrr[c], tol[c] * tol[c] * bb[c], delta);
     }
     const bool update = rule.fire();
+    if (defer && !update && !breakdown) {
+      double k = 8.0;
+      for (int c = 0; c < na; ++c)
+        k = std::min(k, 0.5 * iters_to_event(st.h(c, ST_RR), rr_chk[c], since, maxrr[c], tol[c] * tol[c] * bb[c],
+                                             delta));
+      skip = (int)k;
+    }
+    for (int c = 0; c < na; ++c) rr_chk[c] = st.h(c, ST_RR);
+    since = 0;
     if (update || breakdown || it == maxiter - 1) {
       ++cnt.reliable;
       if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, na, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
@@ -424,7 +439,7 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
       if ((e = st.pull(na))) return e;
       for (int c = 0; c < na; ++c) {
         const double rr = st.h(c, ST_RR);
-        maxrr[c] = rr;
+        maxrr[c] = rr_chk[c] = rr;
         if (rr <= tol[c] * tol[c] * bb[c]) st.h(c, ST_ACTIVE) = 0.0;
       }
       if ((e = cm.compact())) return e;
@@ -1016,14 +1031,22 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
       Vec t = view(tolo, 0, i.ncol);
       return stag_normal_even(env, plo, o, i, t, dm2.as<double>(), 0.0);
     };
-    std::vector<double> tolv(ncol, tol);
+    // target half the tolerance, so the result keeps a margin below it; a
+    // column still above the tolerance (rounding in the last update) goes
+    // round again from its iterate with a tighter target
+    std::vector<double> tolv(ncol, 0.5 * tol);
     ColParam cpm{m2col, dm2.as<double>(), s};  // m^2 per column follows the solver's reordering
-    const int rs = cg_mixed(ble, g, A64, Alo, plo, y, brep, tolv, maxiter, delta, cnt, &cpm);
-    if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
-    status = rs;
     std::vector<double> res;
-    if ((e = rel_residual(ble, A64, y, brep, res, g))) return e;
-    worst = *std::max_element(res.begin(), res.end());
+    for (int pass = 0; pass < 4; ++pass) {
+      const int rs = cg_mixed(ble, g, A64, Alo, plo, y, brep, tolv, maxiter, delta, cnt, &cpm);
+      if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
+      status = rs;
+      if ((e = rel_residual(ble, A64, y, brep, res, g))) return e;
+      worst = *std::max_element(res.begin(), res.end());
+      if (worst <= tol || rs == LQ_ENOCONV) break;
+      for (int k = 0; k < ncol; ++k)
+        if (res[k] > tol) tolv[k] *= std::max(0.05, 0.5 * tol / res[k]);
+    }
     // output
     const size_t colsz = (size_t)2 * g.Vh * 3 * 2;  // doubles per column
     if (launch_fill_zero(x_dev, sizeof(double) * colsz * ncol, s)) return fail(LQ_EDEVICE, "zero");
