@@ -163,6 +163,26 @@ lq_status lq_apply(lq_ctx *ctx, const lq_action *act, const lq_field *g, int op,
 lq_status lq_apply_dev(lq_ctx *ctx, const lq_action *act, const lq_field *g, int op, int prec_bits, int n_rhs,
                        const double *in_dev, double *out_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lq_apply_dev
+ * with no device allocation, free or synchronisation.  Ops: LQ_OP_D,
+ * LQ_OP_DDAG and LQ_OP_HOP for LQ_WILSON, LQ_TM_CLOVER and LQ_HISQ, LQ_OP_HW
+ * and LQ_OP_HOP for LQ_OVERLAP (others: LQ_EINVAL).  The packed input and
+ * output vectors live in a fixed 64 MiB device array of the library (one per
+ * GPU, held until the process ends): 2 x n_rhs x V x 192 bytes (FP64
+ * Wilson-type) must fit, else LQ_EINVAL with the sizes in the message.
+ * Preconditions (else LQ_EINVAL): the field's links at this precision, and
+ * for the twisted-clover D its clover term at this precision, are already on
+ * the device (any earlier lq_apply or lq_solve with them puts them there).
+ * Launch shapes are those an earlier call tuned, else the untuned default;
+ * this call never tunes.  in_dev/out_dev: device arrays in the canonical
+ * layout; the work is enqueued on `stream` and the call returns without
+ * waiting: synchronise the stream before reading out_dev.  Every call on a
+ * GPU uses that GPU's one array, so calls that overlap in time (other
+ * streams, other threads or contexts on the same GPU) race: serialise them. */
+lq_status lq_apply_noalloc(lq_ctx *ctx, const lq_action *act, const lq_field *g, int op, int prec_bits, int n_rhs,
+                           const double *in_dev, double *out_dev, void *stream);
+
 /* Solve D x = b for n_rhs columns to prm->tol relative true residual.
  *   LQ_WILSON:     CG on D^dag D (full lattice)
  *   LQ_TM_CLOVER:  even-odd (symmetric Schur) BiCGStab, sloppy storage + FP64 reliable updates

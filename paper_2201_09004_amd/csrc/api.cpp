@@ -4,6 +4,7 @@
 // the thread-local message read by lq_last_error().
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "lq_internal.h"
@@ -53,6 +54,32 @@ static int check_action(const lq_action* a, const lq_field* f) {
   return 0;
 }
 
+// Device scratch of lq_apply_noalloc (its packed input and output vectors).
+// Each device holds one copy for the life of the process; host code uses the
+// address hipGetSymbolAddress returns on that device, never the symbol.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mtx;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// address of `scratch` on `device` (the current device), looked up once per device
+static int scratch_setup(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(LQ_EINVAL, "device ordinal out of range for the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mtx);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(LQ_EDEVICE, "hipGetSymbolAddress of the allocation-free scratch failed");
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return 0;
+}
+
 static int64_t field_doubles(const lq_field* f, int kind, int n_rhs) {
   const int nc = kind == LQ_HISQ ? 3 : 12;
   return (int64_t)n_rhs * 2 * f->g.Vh * nc * 2;
@@ -76,8 +103,12 @@ lq_status lq_init(int device, lq_ctx** ctx) {
   }
   if (device < 0 || device >= ndev) return (lq_status)fail(LQ_EINVAL, "device ordinal out of range");
   if (hipSetDevice(device) != hipSuccess) return (lq_status)fail(LQ_EDEVICE, "hipSetDevice failed");
+  // the allocation-free entry point's scratch; a failure here only disables that entry point
+  void* scr = nullptr;
+  if (scratch_setup(device, &scr)) scr = nullptr;
   auto* c = new lq_ctx();
   c->device = device;
+  c->scratch = scr;
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return (lq_status)fail(LQ_EDEVICE, "stream creation failed");
@@ -189,6 +220,16 @@ lq_status lq_apply_dev(lq_ctx* c, const lq_action* act, const lq_field* g, int o
   if (n_rhs == 0) return LQ_OK;
   hipSetDevice(c->device);
   return (lq_status)apply_op(c, act, const_cast<lq_field*>(g), op, prec, n_rhs, in, out, (hipStream_t)stream);
+}
+
+lq_status lq_apply_noalloc(lq_ctx* c, const lq_action* act, const lq_field* g, int op, int prec, int n_rhs,
+                           const double* in, double* out, void* stream) {
+  int e = check_apply(c, act, g, prec, n_rhs, in, out);
+  if (e) return (lq_status)e;
+  if (n_rhs == 0) return LQ_OK;
+  hipSetDevice(c->device);
+  return (lq_status)apply_op_noalloc(c, act, const_cast<lq_field*>(g), op, prec, n_rhs, in, out, (hipStream_t)stream,
+                                     c->scratch, kNoallocScratchBytes);
 }
 
 lq_status lq_apply(lq_ctx* c, const lq_action* act, const lq_field* g, int op, int prec, int n_rhs, const double* in,

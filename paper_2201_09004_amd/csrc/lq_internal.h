@@ -46,6 +46,7 @@ struct lq_ctx {
   std::vector<lq::ProfRec> pending;
   std::vector<hipEvent_t> event_pool;
   std::map<std::string, std::pair<int64_t, double>> totals;
+  void* scratch = nullptr;    // this device's address of the allocation-free entry point's scratch
   double* partial = nullptr;  // reduction partials
   size_t partial_bytes = 0;
   std::mutex mtx;
@@ -128,6 +129,9 @@ Vec view(const Vec& v, int c0, int n);  // non-owning view of columns [c0, c0+n)
 int vec_zero(Vec& v);
 int vec_copy(Vec& dst, const Vec& src);  // with precision conversion, same shape
 int vec_swap_cols(Vec& v, int a, int b);  // exchange columns a and b in place
+// bytes make_vec allocates for this shape, and a non-owning Vec over `base`
+size_t vec_bytes(const Geom& g, int prec, int nc, int ncol, int npar);
+Vec vec_at(const Geom& g, int prec, int nc, int ncol, int npar, int par0, void* base, hipStream_t s);
 
 // scoped device buffer
 struct DBuf {
@@ -164,6 +168,7 @@ struct OpEnv {
   double a = 0, b = 0;
   int64_t n_apply = 0;       // stencil half-applications (counted per parity)
   double flops = 0, bytes = 0;
+  bool noalloc = false;      // no device allocation: fields must be resident, shapes are not tuned
 };
 
 int ensure_links(OpEnv& e, int prec);
@@ -208,6 +213,10 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
           double* x_dev, lq_stats* st, hipStream_t s);
 int apply_op(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec, int n_rhs, const double* in_dev,
              double* out_dev, hipStream_t s);
+// apply_op for D, D^dag, the hopping term and H_W with its packed vectors in
+// `scratch` (scratch_bytes long) and no device allocation; enqueue only
+int apply_op_noalloc(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec, int n_rhs,
+                     const double* in_dev, double* out_dev, hipStream_t s, void* scratch, size_t scratch_bytes);
 int hw_spectrum(lq_ctx* c, const lq_action* act, lq_field* f, int iters, HwSpectrum* out, hipStream_t s);
 // certified interval: lmin^2 = theta_min - r_min, lmax^2 = theta_max + r_max
 int hw_bounds(lq_ctx* c, const lq_action* act, lq_field* f, int iters, double* lmin, double* lmax, hipStream_t s);

@@ -90,6 +90,32 @@ Vec make_vec(const Geom& g, int prec, int nc, int ncol, int npar, int par0, hipS
   return v;
 }
 
+size_t vec_bytes(const Geom& g, int prec, int nc, int ncol, int npar) {
+  const size_t nblk = (size_t)ncol * npar;
+  const size_t main = nblk * block_bytes(prec, nc, g.Vh);
+  const size_t nb = prec == 16 ? nblk * g.Vh * sizeof(float) : 0;
+  return (main + 255) / 256 * 256 + nb;
+}
+
+Vec vec_at(const Geom& g, int prec, int nc, int ncol, int npar, int par0, void* base, hipStream_t s) {
+  Vec v;
+  v.prec = prec;
+  v.nc = nc;
+  v.ncol = ncol;
+  v.npar = npar;
+  v.par0 = par0;
+  v.s = s;
+  v.owner = false;
+  v.bytes = vec_bytes(g, prec, nc, ncol, npar);
+  v.f.npar = npar;
+  v.f.Vh = g.Vh;
+  if (ncol == 0) return v;
+  const size_t main = (size_t)ncol * npar * block_bytes(prec, nc, g.Vh);
+  v.f.data = base;
+  v.f.norm = prec == 16 ? (float*)((char*)base + (main + 255) / 256 * 256) : nullptr;
+  return v;
+}
+
 Vec& Vec::operator=(Vec&& o) noexcept {
   if (this != &o) {
     if (f.data && owner) hipFreeAsync(f.data, s);
@@ -176,6 +202,8 @@ int ensure_links(OpEnv& e, int prec) {
   if (f->type == 0) {
     const int rc = (e.recon && prec != 64) ? 1 : 0;
     if (f->links[pi][rc]) return 0;
+    if (e.noalloc) return fail(LQ_EINVAL, "links of this precision are not resident (an earlier lq_apply or lq_solve "
+                                          "at this precision packs them)");
     const int ne = rc ? 6 : 9;
     void* p = nullptr;
     if (hipMalloc(&p, esz * ne * 8 * (size_t)f->g.Vh) != hipSuccess) return fail(LQ_ENOMEM, "link allocation");
@@ -186,6 +214,8 @@ int ensure_links(OpEnv& e, int prec) {
     return 0;
   }
   if (f->fat[pi]) return 0;
+  if (e.noalloc) return fail(LQ_EINVAL, "links of this precision are not resident (an earlier lq_apply or lq_solve "
+                                        "at this precision packs them)");
   double sf = 1.0, sl = 1.0;
   if (prec == 16) {
     const int64_t n = 2 * (int64_t)f->g.Vh * 4 * 18;
@@ -215,6 +245,13 @@ int ensure_clover(OpEnv& e, int prec) {
   lq_field* f = e.f;
   std::lock_guard<std::mutex> lk(f->mtx);
   auto key = std::make_tuple(e.act.m, e.act.c_sw, e.act.mu);
+  if (e.noalloc) {
+    auto it = f->clover.find(key);
+    if (it == f->clover.end() || !it->second.H[pidx(prec)])
+      return fail(LQ_EINVAL, "the clover term of this action and precision is not resident (an earlier lq_apply or "
+                             "lq_solve builds it)");
+    return 0;
+  }
   Clover& c = f->clover[key];
   const size_t nH = 2 * 2 * 18 * (size_t)f->g.Vh, nA = 2 * 2 * 36 * (size_t)f->g.Vh;  // T2 elements
   if (!c.H[0]) {
@@ -321,7 +358,7 @@ static void apply_shape(Args& A, const Shape& sh) {
 
 template <typename Args, typename LaunchFn>
 static int tuned(lq_ctx* c, const std::string& key, Args& A, size_t out_bytes, int prec,
-                 const std::vector<int>& nrs, hipStream_t s, LaunchFn launch) {
+                 const std::vector<int>& nrs, hipStream_t s, LaunchFn launch, bool may_tune = true) {
   const std::vector<int> slabs = slab_candidates(A.g);
   Shape choice{1, 0, 0, 1};
   if (const char* f = getenv("LQ_TUNE_FORCE")) {
@@ -340,6 +377,7 @@ static int tuned(lq_ctx* c, const std::string& key, Args& A, size_t out_bytes, i
     tune_load(c);
     auto it = c->tune.find(key);
     if (it != c->tune.end()) choice = it->second;
+    else if (!may_tune) choice = Shape{1, 0, 0, 1};  // untuned default, not recorded
     else if (!tune_enabled()) c->tune[key] = choice;
     else need = true;
   }
@@ -448,11 +486,11 @@ static int run_wilson(OpEnv& e, WilsonArgs& A, int n_fields, int clov_mats, int 
   // converged columns launch the same kernel at several widths)
   char name_n[64];
   snprintf(name_n, sizeof(name_n), "%s_n%d", name, A.ncol);
-  Prof p(e.ctx, name, e.s);
-  Prof pn(e.ctx, name_n, e.s);
+  Prof p(e.noalloc ? nullptr : e.ctx, name, e.s);
+  Prof pn(e.noalloc ? nullptr : e.ctx, name_n, e.s);
   int r = tuned(e.ctx, key, A, tune_out_bytes(A.prec, 12, A.ncol, out_npar, A.g.Vh), A.prec,
                 nr_candidates(A.prec, A.ncol, blocked), e.s,
-                [](const WilsonArgs& B, hipStream_t st) { return launch_wilson(B, st); });
+                [](const WilsonArgs& B, hipStream_t st) { return launch_wilson(B, st); }, !e.noalloc);
   if (r) return fail(r == -1 ? LQ_ENOTSUP : LQ_EDEVICE, "wilson stencil launch");
   e.n_apply += A.par_out == 2 ? 2 : 1;
   e.flops += (double)nsite * A.ncol * (1320.0 + flops_extra);
@@ -775,10 +813,10 @@ static int run_stag(OpEnv& e, StagArgs& A, int n_fields) {
   // converged columns launch the same kernel at several widths)
   char name_n[64];
   snprintf(name_n, sizeof(name_n), "%s_n%d", name, A.ncol);
-  Prof p(e.ctx, name, e.s);
-  Prof pn(e.ctx, name_n, e.s);
+  Prof p(e.noalloc ? nullptr : e.ctx, name, e.s);
+  Prof pn(e.noalloc ? nullptr : e.ctx, name_n, e.s);
   if (tuned(e.ctx, key, A, tune_out_bytes(A.prec, 3, A.ncol, A.out.npar, A.g.Vh), A.prec, nrs, e.s,
-            [](const StagArgs& B, hipStream_t st) { return launch_stag(B, st); }))
+            [](const StagArgs& B, hipStream_t st) { return launch_stag(B, st); }, !e.noalloc))
     return fail(LQ_EDEVICE, "staggered stencil launch");
   e.n_apply += A.par_out == 2 ? 2 : 1;
   const double rb = A.prec == 64 ? 8 : A.prec == 32 ? 4 : 2;

@@ -1167,6 +1167,46 @@ int apply_op(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec, int
   return hipStreamSynchronize(s) == hipSuccess ? 0 : fail(LQ_EDEVICE, "sync");
 }
 
+int apply_op_noalloc(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec, int n_rhs,
+                     const double* in_dev, double* out_dev, hipStream_t s, void* scratch, size_t scratch_bytes) {
+  const Geom& g = f->g;
+  OpEnv env{c, f, *act, s};
+  env.noalloc = true;
+  env.recon = (prec & LQ_PREC_RECON12) ? 1 : 0;
+  prec &= ~LQ_PREC_RECON12;
+  const int kind = act->kind;
+  const int nc = kind == LQ_HISQ ? 3 : 12;
+  if ((kind == LQ_HISQ) != (f->type == 1)) return fail(LQ_EINVAL, "field type does not match the action");
+  const bool ok_op = op == LQ_OP_D || op == LQ_OP_DDAG || op == LQ_OP_HOP;
+  if (kind == LQ_OVERLAP ? op != LQ_OP_HW && op != LQ_OP_HOP : !ok_op)
+    return fail(LQ_EINVAL, "lq_apply_noalloc: op must be D, D^dag or the hopping term (H_W or the hopping term "
+                           "for overlap)");
+  if (!scratch) return fail(LQ_EDEVICE, "lq_apply_noalloc: scratch not set up on this device");
+  const size_t vb = vec_bytes(g, prec, nc, n_rhs, 2);
+  const size_t vbr = (vb + 255) / 256 * 256;
+  if (2 * vbr > scratch_bytes)
+    return fail(LQ_EINVAL, "lq_apply_noalloc: " + std::to_string(n_rhs) + " columns need " +
+                               std::to_string(2 * vbr) + " bytes of scratch, the maximum is " +
+                               std::to_string(scratch_bytes));
+  Vec in = vec_at(g, prec, nc, n_rhs, 2, 0, scratch, s);
+  Vec out = vec_at(g, prec, nc, n_rhs, 2, 0, (char*)scratch + vbr, s);
+  if (launch_pack_field(g, in_dev, n_rhs, nc, in.f, prec, 2, s)) return fail(LQ_EDEVICE, "pack");
+  int e = 0;
+  if (kind == LQ_HISQ) {
+    if (op == LQ_OP_HOP) e = stag_hop(env, prec, out, in);
+    else e = stag_D(env, prec, out, in, op == LQ_OP_DDAG);
+  } else if (op == LQ_OP_HOP) {
+    e = wilson_hop(env, prec, out, in);
+  } else if (op == LQ_OP_HW) {
+    e = hw_apply(env, prec, out, in);
+  } else {
+    e = wilson_D(env, prec, out, in, op == LQ_OP_DDAG);
+  }
+  if (e) return e;
+  if (launch_unpack_field(g, out.f, prec, n_rhs, nc, out_dev, 2, s)) return fail(LQ_EDEVICE, "unpack");
+  return 0;
+}
+
 // ------------------------------------------------------------------ Lanczos bounds
 static void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, double& lo, double& hi) {
   // bisection with Sturm counts on the symmetric tridiagonal (a diagonal, b off-diagonal)

@@ -27,7 +27,7 @@ LQ_PREC_RECON12 = 0x100
 
 EXPORTS = [
     "lq_init", "lq_finalize", "lq_last_error", "lq_version", "lq_gauge_load", "lq_gauge_load_dev",
-    "lq_hisq_load", "lq_hisq_load_dev", "lq_field_free", "lq_apply", "lq_apply_dev", "lq_solve",
+    "lq_hisq_load", "lq_hisq_load_dev", "lq_field_free", "lq_apply", "lq_apply_dev", "lq_apply_noalloc", "lq_solve",
     "lq_solve_dev", "lq_hw_bounds", "lq_cheb_coeffs", "lq_copy_bandwidth", "lq_profile", "lq_profile_get",
     "lq_server_create", "lq_server_destroy", "lq_submit", "lq_poll", "lq_wait", "lq_server_stats",
 ]
@@ -95,6 +95,7 @@ def load():
         "lq_field_free": ([P], C.c_int),
         "lq_apply": ([P, C.POINTER(lq_action), P, C.c_int, C.c_int, C.c_int, P, P], C.c_int),
         "lq_apply_dev": ([P, C.POINTER(lq_action), P, C.c_int, C.c_int, C.c_int, P, P, P], C.c_int),
+        "lq_apply_noalloc": ([P, C.POINTER(lq_action), P, C.c_int, C.c_int, C.c_int, P, P, P], C.c_int),
         "lq_solve": ([P, C.POINTER(lq_action), P, C.POINTER(lq_params), C.c_int, P, P, C.POINTER(lq_stats)],
                      C.c_int),
         "lq_solve_dev": ([P, C.POINTER(lq_action), P, C.POINTER(lq_params), C.c_int, P, P, C.POINTER(lq_stats),
@@ -235,6 +236,14 @@ def lq_apply(ctx, act, field, op, prec_bits, inp, out=None):
     inp = np.ascontiguousarray(inp)
     out = np.empty_like(inp) if out is None else out
     _check(load().lq_apply(ctx, C.byref(act), field, op, prec_bits, n_rhs, _ptr(inp), _ptr(out)))
+    return out
+
+
+def lq_apply_noalloc(ctx, act, field, op, prec_bits, inp, out):
+    """lq_apply_noalloc on CUDA tensors `inp` and `out` (same shape); enqueued
+    on the current stream of `inp`'s device, not synchronised."""
+    _check(load().lq_apply_noalloc(ctx, C.byref(act), field, op, prec_bits, inp.shape[0], _ptr(inp), _ptr(out),
+                                   _stream_of(inp)))
     return out
 
 
