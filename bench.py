@@ -140,6 +140,61 @@ def copy_peak(L, ctx):
 
 
 # ------------------------------------------------------------------ CPU oracle samples
+def cpu_info():
+    """Host CPU of this run: logical CPUs visible to the process and the model name."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": n, "cpu_count": os.cpu_count(), "model": model}
+
+
+def _tm_slab_worker(seed):
+    """One column's share of the CPU baseline: setup + 2 Schur applications on
+    the 24^3 x 8 slab, one thread; returns the elapsed seconds."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import wilson as W
+
+    slab = (24, 24, 24, 8)
+    U = synth.su3_field(slab, EPS, SEED)
+    b = synth.point_sources(slab)[seed % 12]
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        eo = W.EvenOdd(U, M, CSW, MU)
+        y = eo.mhat(eo.mhat(b))
+        t1 = time.perf_counter()
+    assert np.isfinite(y).all()
+    return t1 - t0
+
+
+def cpu_tm_pool(n_rhs: int, one_core: dict):
+    """The slab sample of cpu_tm run by min(n_rhs, nproc) worker processes at
+    once (one column each): the throughput of the oracle over the machine's cores."""
+    import multiprocessing as mp
+
+    info = cpu_info()
+    nw = max(1, min(n_rhs, info["nproc"] or 1))
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(nw) as pool:
+        per = pool.map(_tm_slab_worker, range(nw))
+    wall = time.perf_counter() - t0
+    # each worker did what one column's extrapolation starts from; scale as cpu_tm does
+    slow = max(per) / (one_core["t_setup_s"] / (TM_LAT[3] / 8) + 2 * one_core["t_schur_s"] / (TM_LAT[3] / 8))
+    return {"workers": nw, "wall_s": round(wall, 2), "worker_s_max": round(max(per), 2),
+            "value": round(one_core["value"] * nw / slow, 8), "unit": "solves/s",
+            "note": ("min(n_rhs, nproc) processes, one column each, at once; per-column time scaled as the "
+                     "one-core sample (slow-down under load x%.2f)" % slow)}
+
+
 def cpu_tm(n_iter_fp64: int, n_rhs: int):
     """FP64 oracle on a 24^3 x 8 slab (1/8 of the volume), one core: setup of
     the even-odd operator plus two Schur applications, scaled to the full
@@ -306,7 +361,13 @@ def bench_tm(args, L, torch):
     if not args.no_cpu:
         log("CPU oracle baseline")
         cpu = cpu_tm(fp64["iters"] if fp64 else max(s["iters"] for s in stats), n_rhs)
+        cpu["host"] = cpu_info()
         log("cpu", cpu)
+        try:
+            cpu["pool"] = cpu_tm_pool(n_rhs, cpu)
+        except Exception as e:  # noqa: BLE001
+            cpu["pool"] = {"error": repr(e)}
+        log("cpu pool", cpu["pool"])
     L.lq_field_free(field)
     L.lq_finalize(ctx)
     return {
@@ -319,6 +380,10 @@ def bench_tm(args, L, torch):
         "roofline": roof, "cpu_baseline": cpu,
         "converged": ok, "worst_true_rel_res": worst,
         "iters": [s["iters"] for s in stats], "reliable_updates": [s["reliable_updates"] for s in stats],
+        # dslash rate: standard 1320 flops per output site and column (hopping term) of
+        # the dominant stencil at 12 columns, and all stencil flops of the solve over its wall time
+        "dslash_gflops": round(1320.0 * n_rhs * Vh / (roof["avg_ms"] * 1e-3) / 1e9, 1),
+        "solve_stencil_gflops": round(sum(s["gflops"] for s in stats) / len(stats), 1),
         "fp64_single_column": fp64,
         "speedup_vs_fp64_single_column": (value / fp64["solves_per_s"]) if fp64 else None,
         "kernels": kernels,
