@@ -98,3 +98,33 @@ def hw_extremes(U, rho, antiperiodic=True, tol=1e-10):
     lmax = eigsh(op, k=1, which="LA", tol=tol, return_eigenvectors=False)[0]
     lmin = eigsh(op, k=1, which="SA", tol=tol, return_eigenvectors=False)[0]
     return float(np.sqrt(lmin)), float(np.sqrt(lmax))
+
+
+# ------------------------------------------------------------------ low modes (sec. 2.3)
+def hw_low_modes_dense(U, rho, n, antiperiodic=True):
+    """The n eigenpairs of H_W with the smallest |lambda| (dense numpy eigh;
+    small lattices only).  Returns (lam[n], vecs[n][T,Z,Y,X,4,3]), |lam| ascending."""
+    from .dense import wilson_tm_clover_dense
+    from .lattice import GAMMA5 as G5
+    D = wilson_tm_clover_dense(U, -rho, antiperiodic=antiperiodic)
+    V = D.shape[0] // 12
+    H = np.kron(np.eye(V), np.kron(G5, np.eye(3))) @ D
+    w, Q = np.linalg.eigh(H)
+    order = np.argsort(np.abs(w), kind="stable")[:n]
+    shp = U.shape[:4] + (4, 3)
+    return w[order], np.array([Q[:, i].reshape(shp) for i in order])
+
+
+def sign_hw_projected(U, psi, rho, c, a, b, lam, vecs, antiperiodic=True):
+    """eps(H_W) psi with the low modes (lam, vecs) treated exactly and the
+    Chebyshev approximation on the rest (sec. 2.3):
+        eps psi = sum_i sign(lam_i) u_i <u_i, psi> + P eps_N(H_W) P psi,
+    P = 1 - sum_i u_i u_i^dag (the projection is applied on both sides of
+    the polynomial, which maps the projected space to itself only exactly)."""
+    def proj(v):
+        out = v.copy()
+        for u in vecs:
+            out = out - u * np.vdot(u, v)
+        return out
+    low = sum(np.sign(l) * u * np.vdot(u, psi) for l, u in zip(lam, vecs))
+    return low + proj(sign_hw(U, proj(psi), rho, c, a, b, antiperiodic))

@@ -187,3 +187,31 @@ def test_golden_hw_spectra_come_from_the_oracle():
     U = synth.su3_field(tuple(e["L"]), e["eps"], e["seed"])
     lo, hi = OV.hw_extremes(U, e["rho"], tol=1e-8)
     assert abs(lo - e["lmin"]) < 1e-7 * lo and abs(hi - e["lmax"]) < 1e-7 * hi
+
+
+def test_low_mode_projected_sign_2x4():
+    """Low-mode projection (sec. 2.3): with the n smallest |lambda| modes of
+    H_W treated exactly, a Chebyshev interval that starts above them
+    (0.9 lambda_{n+1}^2) gives the exact sign function within the polynomial
+    bound, while the same polynomial without the projection does not (its
+    interval misses the projected modes)."""
+    L = (2, 2, 2, 2)
+    U = synth.su3_field(L, 0.3, 251)
+    H = _dense_hw(U)
+    w, Q = np.linalg.eigh(H)
+    lam, vecs = OV.hw_low_modes_dense(U, RHO, 25)
+    order = np.argsort(np.abs(w))
+    assert np.allclose(np.abs(lam), np.abs(w[order[:25]]), atol=1e-12)
+    n = 24  # project 24, the 25th sets the interval
+    a, b = 0.9 * lam[n] ** 2, 1.1 * np.abs(w).max() ** 2
+    c = OV.cheb_coeffs(a, b, 80)
+    delta = OV.sign_deviation(c, a, b)
+    v = synth.gaussian_spinor(L, 1, 252)[0]
+    exact = (Q @ (np.sign(w) * (Q.conj().T @ v.ravel()))).reshape(v.shape)
+    got = OV.sign_hw_projected(U, v, RHO, c, a, b, lam[:n], vecs[:n])
+    assert lat.norm(got - exact) <= 1.01 * delta * lat.norm(v) + 1e-12
+    bad = OV.sign_hw(U, v, RHO, c, a, b)
+    assert lat.norm(bad - exact) > 100 * delta * lat.norm(v)
+    # the projected modes are eigenvectors: H u = lam u
+    for l, u in zip(lam[:n], vecs[:n]):
+        assert lat.norm(OV.hw(U, u, RHO) - l * u) < 1e-12
