@@ -88,6 +88,12 @@ typedef struct {
                            refused with LQ_EINVAL) */
   const double *cheb_c; /* overlap: N+1 coefficients (host), or NULL: the library
                            interpolates y^(-1/2) at the Chebyshev nodes of [a,b] */
+  int32_t n_lowmodes; /* overlap: low modes of H_W treated exactly in the sign function
+                         (sec. 2.3): eps v = sum_i sign(lambda_i) u_i <u_i, v> + P eps_N(H_W) P v,
+                         P = 1 - sum_i u_i u_i^dag, over the n_lowmodes smallest |lambda| of the
+                         field's resident modes (lq_eigs with LQ_EIG_HW, which must hold at least
+                         n_lowmodes + 1; else LQ_EINVAL).  With no interval given, a = 0.9 times
+                         the square of the next mode's eigenvalue.  0: no projection. */
 } lq_action;
 
 /* operator selector for lq_apply (the result is written for every site of
@@ -119,6 +125,9 @@ typedef struct {
   int32_t fault_inject;    /* testing: 1 NaN in the first reduction, 2 allocation failure, 3 maxiter=1 */
   int32_t solver;          /* 0: default for the action, 1: CG on normal equations D^dag D (full lattice,
                               twisted clover and overlap) */
+  int32_t deflate;         /* overlap (solver 0): use this many resident chiral-sector low modes per
+                              chirality (lq_eigs with LQ_EIG_OVERLAP) for the initial guess of every
+                              sector solve; 0: none */
 } lq_params;
 
 typedef struct {
@@ -214,6 +223,27 @@ lq_status lq_solve_dev(lq_ctx *ctx, const lq_action *act, const lq_field *g, con
  * smallest Ritz pair has not converged (r_min >= theta_min / 2) or iters < 2. */
 lq_status lq_hw_bounds(lq_ctx *ctx, const lq_action *act, const lq_field *g, int iters, double *lmin,
                        double *lmax);
+/* Low modes (sec. 2.3), computed on the device and kept resident with the field
+ * (replacing an earlier set of the same kind and rho) until lq_field_free:
+ *   LQ_EIG_HW       the nev eigenpairs of H_W = g5 D_W(-rho) with the smallest |lambda|
+ *                   (for lq_action.n_lowmodes); evals[nev] ascending in |lambda|.  Lanczos with
+ *                   implicit restarts (shifted QR steps on the tridiagonal Hessenberg matrix) on
+ *                   the Chebyshev polynomial T_d(Z(H_W^2)) that maps [filter_cut, b] onto [-1, 1]
+ *                   (filter_degree d, 0: 24; filter_cut 0: 4 times the smallest eigenvalue of
+ *                   H_W^2), then a Rayleigh-Ritz step with H_W.  LQ_EINVAL if a found mode lies
+ *                   above the cut (raise filter_cut).
+ *   LQ_EIG_OVERLAP  the nev smallest eigenpairs of the chirally projected D(0)^dag D(0) =
+ *                   2 rho^2 (1 + s P_s eps P_s) in each chirality s = +1, -1 (for
+ *                   lq_params.deflate), with the action's sign function (FP64);
+ *                   evals[2 nev]: s = +1 then s = -1, each ascending.
+ * tol: residual target |A u - lambda u| relative to the operator norm (0: 1e-10);
+ * max_restarts (0: 200).  stats: iters = restarts, n_apply = operator applications,
+ * true_rel_res = largest residual.  LQ_ENOCONV: the modes are stored, some residual is
+ * above tol. */
+enum { LQ_EIG_HW = 0, LQ_EIG_OVERLAP = 1 };
+lq_status lq_eigs(lq_ctx *ctx, const lq_action *act, const lq_field *g, int which, int nev, double tol,
+                  int max_restarts, int filter_degree, double filter_cut, double *evals, lq_stats *stats);
+
 /* Coefficients c_0..c_N of the Chebyshev interpolant of y^(-1/2) on [a, b] (host, FP64). */
 lq_status lq_cheb_coeffs(double a, double b, int N, double *c);
 

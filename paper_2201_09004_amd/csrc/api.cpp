@@ -48,6 +48,7 @@ static int check_action(const lq_action* a, const lq_field* f) {
     if (a->cheb_N < 1 || a->cheb_N > 100000) return fail(LQ_EINVAL, "overlap: cheb_N out of range");
     if ((a->cheb_a != 0 || a->cheb_b != 0) && !(a->cheb_a > 0 && a->cheb_b > a->cheb_a))
       return fail(LQ_EINVAL, "overlap: need 0 < cheb_a < cheb_b");
+    if (a->n_lowmodes < 0 || a->n_lowmodes > 1000) return fail(LQ_EINVAL, "overlap: n_lowmodes out of range");
   }
   if (!std::isfinite(a->m) || !std::isfinite(a->mu) || !std::isfinite(a->c_sw))
     return fail(LQ_EINVAL, "non-finite action parameter");
@@ -128,6 +129,7 @@ lq_status lq_finalize(lq_ctx* c) {
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
   prof_flush(c);
+  eig_release(c);
   for (auto e : c->event_pool) hipEventDestroy(e);
   if (c->partial) hipFree(c->partial);
   hipStreamDestroy(c->stream);
@@ -197,6 +199,7 @@ lq_status lq_field_free(lq_field* f) {
     for (auto p : kv.second.H) fr(p);
     for (auto p : kv.second.Ainv) fr(p);
   }
+  for (auto& kv : f->eig) fr(kv.second.vecs);
   delete f;
   return LQ_OK;
 }
@@ -309,6 +312,18 @@ lq_status lq_solve(lq_ctx* c, const lq_action* act, const lq_field* g, const lq_
     return (lq_status)fail(LQ_EDEVICE, "download");
   g_err = msg;
   return (lq_status)e;
+}
+
+lq_status lq_eigs(lq_ctx* c, const lq_action* act, const lq_field* g, int which, int nev, double tol,
+                  int max_restarts, int filter_degree, double filter_cut, double* evals, lq_stats* stats) {
+  if (!c) return (lq_status)fail(LQ_EINVAL, "ctx is NULL");
+  int e = check_action(act, g);
+  if (e) return (lq_status)e;
+  if (act->kind != LQ_OVERLAP) return (lq_status)fail(LQ_EINVAL, "lq_eigs needs the overlap action");
+  if (!(act->rho > 0)) return (lq_status)fail(LQ_EINVAL, "lq_eigs: rho must be positive");
+  hipSetDevice(c->device);
+  return (lq_status)eigs(c, act, const_cast<lq_field*>(g), which, nev, tol, max_restarts, filter_degree, filter_cut,
+                         evals, stats, c->stream);
 }
 
 lq_status lq_hw_bounds(lq_ctx* c, const lq_action* act, const lq_field* g, int iters, double* lmin, double* lmax) {

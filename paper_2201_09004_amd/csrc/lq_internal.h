@@ -47,6 +47,7 @@ struct lq_ctx {
   std::vector<hipEvent_t> event_pool;
   std::map<std::string, std::pair<int64_t, double>> totals;
   void* scratch = nullptr;    // this device's address of the allocation-free entry point's scratch
+  void* rocblas = nullptr;    // rocBLAS handle of the eigensolver (created on first use)
   double* partial = nullptr;  // reduction partials
   size_t partial_bytes = 0;
   std::mutex mtx;
@@ -70,6 +71,16 @@ struct HwSpectrum {
   int steps;
 };
 
+// Resident low modes of a field: eigenvectors (FP64 Wilson-type columns, both
+// parities, make_vec layout) of H_W (which = LQ_EIG_HW, chir = 0) or of the
+// chiral-sector overlap operator (LQ_EIG_OVERLAP, chir = +-1) for one rho
+struct EigSet {
+  int which = 0, chir = 0, n = 0;
+  double rho = 0;
+  void* vecs = nullptr;
+  std::vector<double> vals, res;  // eigenvalues (H_W: ascending |lambda|; sector: ascending) and residuals
+};
+
 }  // namespace lq
 
 struct lq_field {
@@ -84,6 +95,7 @@ struct lq_field {
   float sfat[3] = {1, 1, 1}, slng[3] = {1, 1, 1};
   std::map<std::tuple<double, double, double>, lq::Clover> clover;
   std::map<double, lq::HwSpectrum> hw_spec;  // per rho: Lanczos spectrum of H_W^2
+  std::map<std::tuple<int, double, int>, lq::EigSet> eig;  // (which, rho, chirality): low modes
   std::mutex mtx;
 };
 
@@ -187,6 +199,8 @@ int tm_schur_reconstruct(OpEnv& e, Vec& x, const Vec& x_e, const Vec& b); // FP6
 // overlap
 int hw_apply(OpEnv& e, int prec, Vec& out, const Vec& in);
 int sign_apply(OpEnv& e, int prec, Vec& out, const Vec& in);
+// Chebyshev filter T_d(Z(H_W^2)) v, Z = (2 H_W^2 - (lo + hi)) / (hi - lo), FP64
+int cheb_filter(OpEnv& e, Vec& out, const Vec& in, double lo, double hi, int d);
 int overlap_D(OpEnv& e, int prec, Vec& out, const Vec& in, bool dag);
 int overlap_prepare(OpEnv& e);
 // staggered
@@ -221,5 +235,16 @@ int hw_spectrum(lq_ctx* c, const lq_action* act, lq_field* f, int iters, HwSpect
 // certified interval: lmin^2 = theta_min - r_min, lmax^2 = theta_max + r_max
 int hw_bounds(lq_ctx* c, const lq_action* act, lq_field* f, int iters, double* lmin, double* lmax, hipStream_t s);
 void cheb_coeffs(double a, double b, int N, double* c);
+
+// low modes (eig.cpp)
+int eigs(lq_ctx* c, const lq_action* act, lq_field* f, int which, int nev, double tol, int max_restarts, int degree,
+         double cut, double* evals, lq_stats* st, hipStream_t s);
+const EigSet* find_eigs(lq_field* f, int which, double rho, int chir);
+// v <- (1 - U U^H) v over the first n modes; coef (device, n x v.ncol complex) <- U^H v
+int project_out(lq_ctx* c, const Geom& g, hipStream_t s, const EigSet& es, int n, Vec& v, void* coef);
+// v += U diag(w) coef, w[col * n + i] (host)
+int add_modes(lq_ctx* c, const Geom& g, hipStream_t s, const EigSet& es, int n, const std::vector<double>& w,
+              Vec& v, void* coef);
+void eig_release(lq_ctx* c);
 
 }  // namespace lq

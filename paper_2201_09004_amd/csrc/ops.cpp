@@ -692,7 +692,19 @@ int overlap_prepare(OpEnv& e) {
     e.f->hw_spec[e.act.rho] = sp;
   }
   double a = e.act.cheb_a, b = e.act.cheb_b;
-  if (a > 0 && b > a) {
+  const int nl = e.act.n_lowmodes;
+  if (nl > 0) {
+    // low modes treated exactly: the polynomial must hold the rest of the spectrum
+    const EigSet* es = find_eigs(e.f, LQ_EIG_HW, e.act.rho, 0);
+    if (!es || es->n < nl + 1)
+      return fail(LQ_EINVAL, "overlap: n_lowmodes needs at least n_lowmodes + 1 resident H_W modes (lq_eigs)");
+    if (!(a > 0 && b > a)) {
+      a = 0.9 * es->vals[nl] * es->vals[nl];
+      b = 1.1 * (sp.theta_max + sp.r_max);
+    } else if (sp.theta_max > b || a > es->vals[nl] * es->vals[nl]) {
+      return fail(LQ_EINVAL, "overlap: the Chebyshev interval does not hold the spectrum outside the low modes");
+    }
+  } else if (a > 0 && b > a) {
     if (sp.theta_min < a || sp.theta_max > b)
       return fail(LQ_EINVAL, "overlap: the Chebyshev interval [" + std::to_string(a) + ", " + std::to_string(b) +
                                  "] does not hold the spectrum of H_W^2 (Ritz values " +
@@ -709,9 +721,42 @@ int overlap_prepare(OpEnv& e) {
   return 0;
 }
 
+static int sign_poly(OpEnv& e, int prec, Vec& out, const Vec& in);
+
+// eps(H_W) v; with n_lowmodes > 0 the low modes of H_W enter exactly:
+// eps v = sum_i sign(lambda_i) u_i <u_i, v> + P eps_N(H_W) P v, with the
+// projections and the low-mode part in FP64 and the polynomial in `prec`
 int sign_apply(OpEnv& e, int prec, Vec& out, const Vec& in) {
   int r = overlap_prepare(e);
-  if (!r) r = ensure_links(e, prec);
+  if (r) return r;
+  const int nl = e.act.n_lowmodes;
+  if (nl <= 0) return sign_poly(e, prec, out, in);
+  const Geom& g = e.f->g;
+  const EigSet* es = find_eigs(e.f, LQ_EIG_HW, e.act.rho, 0);
+  if (!es || es->n < nl) return fail(LQ_EINVAL, "overlap: low modes not resident");
+  Vec v64 = make_vec(g, 64, 12, in.ncol, 2, 0, e.s), o64 = make_vec(g, 64, 12, in.ncol, 2, 0, e.s);
+  DBuf coef(sizeof(double) * 2 * nl * std::max(in.ncol, 1), e.s), junk(sizeof(double) * 2 * nl * std::max(in.ncol, 1), e.s);
+  if (!v64.ok() || !o64.ok() || !coef.p || !junk.p) return fail(LQ_ENOMEM, "projection buffers");
+  if ((r = vec_copy(v64, in))) return r;
+  if ((r = project_out(e.ctx, g, e.s, *es, nl, v64, coef.p))) return r;
+  if (prec == 64) {
+    if ((r = sign_poly(e, 64, o64, v64))) return r;
+  } else {
+    Vec vl = make_vec(g, prec, 12, in.ncol, 2, 0, e.s), ol = make_vec(g, prec, 12, in.ncol, 2, 0, e.s);
+    if (!vl.ok() || !ol.ok()) return fail(LQ_ENOMEM, "projection buffers");
+    if ((r = vec_copy(vl, v64)) || (r = sign_poly(e, prec, ol, vl)) || (r = vec_copy(o64, ol))) return r;
+  }
+  if ((r = project_out(e.ctx, g, e.s, *es, nl, o64, junk.p))) return r;
+  std::vector<double> w((size_t)nl * in.ncol);
+  for (int col = 0; col < in.ncol; ++col)
+    for (int i = 0; i < nl; ++i) w[(size_t)col * nl + i] = es->vals[i] >= 0 ? 1.0 : -1.0;
+  if ((r = add_modes(e.ctx, g, e.s, *es, nl, w, o64, coef.p))) return r;
+  return vec_copy(out, o64);
+}
+
+// eps_N(H_W) v by Clenshaw's recursion (no projection)
+static int sign_poly(OpEnv& e, int prec, Vec& out, const Vec& in) {
+  int r = ensure_links(e, prec);
   if (r) return r;
   const Geom& g = e.f->g;
   const int N = (int)e.cheb.size() - 1;
@@ -762,6 +807,42 @@ int sign_apply(OpEnv& e, int prec, Vec& out, const Vec& in) {
   (void)A;
   // bk1 now holds y = sum_k c_k T_k(Z) v
   return hw_apply(e, prec, out, bk1);
+}
+
+int cheb_filter(OpEnv& e, Vec& out, const Vec& in, double lo, double hi, int d) {
+  int r = ensure_links(e, 64);
+  if (r) return r;
+  const Geom& g = e.f->g;
+  // T_0 = v, T_1 = Z v, T_{j+1} = 2 Z T_j - T_{j-1}: each step one H_W and one
+  // stencil with the Clenshaw epilogue (c_k = 0)
+  Vec t0 = make_vec(g, 64, 12, in.ncol, 2, 0, e.s), t1 = make_vec(g, 64, 12, in.ncol, 2, 0, e.s),
+      w = make_vec(g, 64, 12, in.ncol, 2, 0, e.s);
+  if (!t0.ok() || !t1.ok() || !w.ok()) return fail(LQ_ENOMEM, "filter buffers");
+  if ((r = vec_copy(t0, in)) || (r = vec_zero(t1))) return r;
+  WilsonArgs W{};
+  W.prec = 64;
+  W.par_out = 2;
+  W.ncol = in.ncol;
+  W.links = links_for(e, 64);
+  W.a = 4.0 - e.act.rho;
+  W.k_hop = -0.5;
+  W.epi = EPI_CHEB;
+  W.ck = 0.0;
+  for (int j = 0; j < d; ++j) {
+    // t1 <- s1 H(H t0) + s2 t0 - t1 (j = 0: Z v with the halved factors, t1 = 0)
+    if ((r = hw_apply(e, 64, w, t0))) return r;
+    W.in = w.f;
+    W.x = w.f;
+    W.v = t0.f;
+    W.b1 = t0.f;
+    W.b2 = t1.f;
+    W.out = t1.f;
+    W.s1 = (j == 0 ? 2.0 : 4.0) / (hi - lo);
+    W.s2 = (j == 0 ? -1.0 : -2.0) * (lo + hi) / (hi - lo);
+    if ((r = run_wilson(e, W, 6, 0, 96))) return r;
+    std::swap(t0, t1);  // t0 = T_{j+1}, t1 = T_j
+  }
+  return vec_copy(out, t0);
 }
 
 int overlap_D(OpEnv& e, int prec, Vec& out, const Vec& in, bool dag) {

@@ -737,6 +737,28 @@ static int overlap_solve(OpEnv& env, const lq_params* prm, int n_rhs, const doub
       }
     }
 
+    // deflation: the initial guess from the resident low modes of each column's
+    // chiral sector, z0 = sum_i u_i <u_i, src> / (f mu_i + m^2), for the columns
+    // that do not start from the multi-shift solution
+    const bool from_ms = !have_r && nm > 1;
+    if (prm->deflate > 0 && !from_ms) {
+      for (int q = 0; q < ncs; ++q) {
+        const EigSet* es = find_eigs(env.f, LQ_EIG_OVERLAP, rho, cols[q].s);
+        if (!es || es->n < prm->deflate)
+          return fail(LQ_EINVAL, "overlap: deflate needs that many resident sector modes (lq_eigs LQ_EIG_OVERLAP)");
+        const int nd = prm->deflate;
+        const double mq = mass[cols[q].i], fq = 1.0 - mq * mq / (4.0 * rho * rho);
+        Vec sq = make_vec(g, 64, 12, 1, 2, 0, s), zq = view(z, q, 1);
+        DBuf cf(sizeof(double) * 2 * nd, s);
+        if (!sq.ok() || !cf.p) return fail(LQ_ENOMEM, "deflation buffers");
+        Vec srcq = view(src, q, 1);
+        if ((e = vec_copy(sq, srcq)) || (e = project_out(c, g, s, *es, nd, sq, cf.p))) return e;
+        std::vector<double> wts(nd);
+        for (int i = 0; i < nd; ++i) wts[i] = 1.0 / (fq * es->vals[i] + mq * mq);
+        if ((e = vec_zero(zq)) || (e = add_modes(c, g, s, *es, nd, wts, zq, cf.p))) return e;
+      }
+    }
+
     // sector solve with FP64 reliable updates (the sector operator per column)
     Vec e64 = make_vec(g, 64, 12, ncs, 2, 0, s), elo = make_vec(g, plo, 12, ncs, 2, 0, s);
     if (!e64.ok() || !elo.ok()) return fail(LQ_ENOMEM, "overlap sector buffers");

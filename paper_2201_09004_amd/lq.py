@@ -28,7 +28,7 @@ LQ_PREC_RECON12 = 0x100
 EXPORTS = [
     "lq_init", "lq_finalize", "lq_last_error", "lq_version", "lq_gauge_load", "lq_gauge_load_dev",
     "lq_hisq_load", "lq_hisq_load_dev", "lq_field_free", "lq_apply", "lq_apply_dev", "lq_apply_noalloc", "lq_solve",
-    "lq_solve_dev", "lq_hw_bounds", "lq_cheb_coeffs", "lq_copy_bandwidth", "lq_profile", "lq_profile_get",
+    "lq_solve_dev", "lq_eigs", "lq_hw_bounds", "lq_cheb_coeffs", "lq_copy_bandwidth", "lq_profile", "lq_profile_get",
     "lq_server_create", "lq_server_destroy", "lq_submit", "lq_poll", "lq_wait", "lq_server_stats",
 ]
 
@@ -46,14 +46,14 @@ class lq_geom(C.Structure):
 class lq_action(C.Structure):
     _fields_ = [("kind", C.c_int32), ("m", C.c_double), ("mu", C.c_double), ("c_sw", C.c_double),
                 ("rho", C.c_double), ("cheb_N", C.c_int32), ("cheb_a", C.c_double), ("cheb_b", C.c_double),
-                ("cheb_c", C.POINTER(C.c_double))]
+                ("cheb_c", C.POINTER(C.c_double)), ("n_lowmodes", C.c_int32)]
 
 
 class lq_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("sloppy_bits", C.c_int32),
                 ("reliable_delta", C.c_double), ("n_shift", C.c_int32), ("masses", C.POINTER(C.c_double)),
                 ("reconstruct_full", C.c_int32), ("recon12", C.c_int32), ("use_initial_guess", C.c_int32),
-                ("fault_inject", C.c_int32), ("solver", C.c_int32)]
+                ("fault_inject", C.c_int32), ("solver", C.c_int32), ("deflate", C.c_int32)]
 
 
 class lq_stats(C.Structure):
@@ -101,6 +101,8 @@ def load():
         "lq_solve_dev": ([P, C.POINTER(lq_action), P, C.POINTER(lq_params), C.c_int, P, P, C.POINTER(lq_stats),
                           P], C.c_int),
         "lq_hw_bounds": ([P, C.POINTER(lq_action), P, C.c_int, D, D], C.c_int),
+        "lq_eigs": ([P, C.POINTER(lq_action), P, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_double, D,
+                     C.POINTER(lq_stats)], C.c_int),
         "lq_cheb_coeffs": ([C.c_double, C.c_double, C.c_int, D], C.c_int),
         "lq_copy_bandwidth": ([P, C.c_size_t, C.c_int, D], C.c_int),
         "lq_profile": ([P, C.c_int], C.c_int),
@@ -162,8 +164,9 @@ def geom(L, antiperiodic=True):
     return g
 
 
-def action(kind, m=0.0, mu=0.0, c_sw=0.0, rho=0.0, cheb_N=0, cheb_a=0.0, cheb_b=0.0, cheb_c=None):
-    a = lq_action(kind=kind, m=m, mu=mu, c_sw=c_sw, rho=rho, cheb_N=cheb_N, cheb_a=cheb_a, cheb_b=cheb_b)
+def action(kind, m=0.0, mu=0.0, c_sw=0.0, rho=0.0, cheb_N=0, cheb_a=0.0, cheb_b=0.0, cheb_c=None, n_lowmodes=0):
+    a = lq_action(kind=kind, m=m, mu=mu, c_sw=c_sw, rho=rho, cheb_N=cheb_N, cheb_a=cheb_a, cheb_b=cheb_b,
+                  n_lowmodes=n_lowmodes)
     if cheb_c is not None:
         arr = np.ascontiguousarray(cheb_c, dtype=np.float64)
         a._keep = arr
@@ -172,10 +175,10 @@ def action(kind, m=0.0, mu=0.0, c_sw=0.0, rho=0.0, cheb_N=0, cheb_a=0.0, cheb_b=
 
 
 def params(tol=1e-10, maxiter=0, sloppy_bits=64, reliable_delta=0.0, masses=None, reconstruct_full=0,
-           recon12=0, use_initial_guess=0, fault_inject=0, solver=0):
+           recon12=0, use_initial_guess=0, fault_inject=0, solver=0, deflate=0):
     p = lq_params(tol=tol, maxiter=maxiter, sloppy_bits=sloppy_bits, reliable_delta=reliable_delta,
                   reconstruct_full=reconstruct_full, recon12=recon12, use_initial_guess=use_initial_guess,
-                  fault_inject=fault_inject, solver=solver)
+                  fault_inject=fault_inject, solver=solver, deflate=deflate)
     if masses is not None:
         arr = np.ascontiguousarray(masses, dtype=np.float64)
         p._keep = arr
@@ -270,6 +273,21 @@ def lq_solve(ctx, act, field, prm, b, x=None):
         code = load().lq_solve(ctx, C.byref(act), field, C.byref(prm), n_rhs, _ptr(b), _ptr(x), C.byref(st))
     _check(code, ok=(LQ_OK, LQ_ENOCONV))
     return x, st.as_dict()
+
+
+LQ_EIG_HW, LQ_EIG_OVERLAP = 0, 1
+
+
+def lq_eigs(ctx, act, field, which, nev, tol=1e-10, max_restarts=0, filter_degree=0, filter_cut=0.0):
+    """Low modes kept resident with the field; returns (eigenvalues, stats dict).
+    LQ_ENOCONV (modes stored, a residual above tol) is returned in stats['status']."""
+    n = nev * (2 if which == LQ_EIG_OVERLAP else 1)
+    ev = np.zeros(n)
+    st = lq_stats()
+    code = load().lq_eigs(ctx, C.byref(act), field, which, nev, tol, max_restarts, filter_degree, filter_cut,
+                          ev.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st))
+    _check(code, ok=(LQ_OK, LQ_ENOCONV))
+    return ev, st.as_dict()
 
 
 def lq_hw_bounds(ctx, act, field, iters=200):

@@ -56,7 +56,7 @@ def test_struct_layouts_match_header(lib):
     import ctypes as C
     # sizes follow the natural C layout of the structs in include/lq.h
     assert C.sizeof(L.lq_geom) == 20
-    assert C.sizeof(L.lq_action) == 72
+    assert C.sizeof(L.lq_action) == 80
     assert C.sizeof(L.lq_stats) == 48
 
 
