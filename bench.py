@@ -20,6 +20,11 @@ Other workloads (--workload):
            (multi-shift CG in the chiral sector, then per-mass refinement)
   overlap_sign  one application of the order-200 sign function eps(H_W) to
            12 columns in FP16 storage (sec. 2.3, Fig. 2)
+  overlap_lowmodes  the 16 lowest |lambda| eigenpairs of H_W at 24^3 x 64
+           (Chebyshev-filtered implicitly restarted Lanczos) and the order-200
+           FP16 sign function with them treated exactly
+  overlap_deflated  8 chiral-sector low modes of the overlap operator per
+           chirality, then the overlap workload's propagator with deflation
   serve    the serving loop: Poisson arrivals of 12-column twisted-clover and
            HISQ requests on 16^3x32, 24^3x64 and 32^3x64, p50/p99 latency
   wilson   plain Wilson CG on the normal equations, FP64, 8^4, kappa = 0.12
@@ -692,6 +697,109 @@ def bench_overlap_mm(args, L, torch):
                               "overlap_multimass_chiral_cg_24x24x24x64_12rhs_3mass_cheb200_fp16")
 
 
+def _overlap_setup(L, torch):
+    import synth
+    dev = torch.device("cuda:0")
+    U = synth.su3_field(OV_LAT, EPS, SEED)
+    U_d = torch.from_numpy(U).to(dev)
+    del U
+    ctx = L.lq_init(0)
+    field = L.lq_gauge_load(ctx, OV_LAT, U_d)
+    del U_d
+    torch.cuda.empty_cache()
+    return ctx, field
+
+
+def bench_overlap_lowmodes(args, L, torch):
+    """Low modes of H_W (sec. 2.3) at the overlap workload's size and their use
+    in the sign function: eigensolver time and accuracy, then the FP16 order-200
+    sign function on 12 point sources with 15 modes treated exactly."""
+    import synth
+
+    nev, n_rhs = 16, 12
+    ctx, field = _overlap_setup(L, torch)
+    act = L.action(L.LQ_OVERLAP, m=OV_M, rho=OV_RHO, cheb_N=OV_N)
+    t0 = time.perf_counter()
+    ev, st = L.lq_eigs(ctx, act, field, L.LQ_EIG_HW, nev, tol=1e-10)
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    log("H_W low modes", ev, st, t_eig, "s")
+    v_d = torch.from_numpy(synth.point_sources(OV_LAT)).to(torch.device("cuda:0"))
+    proj = L.action(L.LQ_OVERLAP, m=OV_M, rho=OV_RHO, cheb_N=OV_N, n_lowmodes=nev - 1)
+    out = torch.empty_like(v_d)
+    for _ in range(args.warmup):
+        L.lq_apply(ctx, proj, field, L.LQ_OP_SIGN, 16, v_d, out)
+    torch.cuda.synchronize()
+    L.lq_profile(ctx, True)
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        L.lq_apply(ctx, proj, field, L.LQ_OP_SIGN, 16, v_d, out)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    kernels = profile_table(L, ctx, ["wilson16_cheb", "wilson16_xpay_g5", "blas"])
+    L.lq_profile(ctx, False)
+    ref = torch.empty_like(v_d)
+    L.lq_apply(ctx, proj, field, L.LQ_OP_SIGN, 64, v_d, ref)
+    torch.cuda.synchronize()
+    rel16 = float(torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref))
+    L.lq_field_free(field)
+    L.lq_finalize(ctx)
+    ms = (t2 - t1) / args.steps * 1e3
+    return {
+        "metric": METRIC, "value": round(n_rhs * args.steps / (t2 - t1), 4), "unit": "column-applications/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+        "config": {"workload": "overlap_lowmodes_hw16_24x24x24x64_cheb200_fp16", "lattice": list(OV_LAT),
+                   "nev": nev, "n_lowmodes": nev - 1, "rho": OV_RHO, "N": OV_N},
+        "roofline": None, "cpu_baseline": None,
+        "eigensolver": {"seconds": round(t_eig, 2), "restarts": st["iters"], "hw_applications": st["n_apply"],
+                        "max_residual": st["true_rel_res"], "eigenvalues": [float(x) for x in ev]},
+        "fp16_vs_fp64_projected_rel_l2": rel16, "kernels": kernels,
+    }
+
+
+def bench_overlap_deflated(args, L, torch):
+    """Deflated overlap propagator (sec. 2.3): 8 low modes of the chirally
+    projected overlap operator per chirality (FP32 sign function, residual
+    1e-6), then the overlap workload's 12-column solve with them as the
+    initial guess of every sector solve."""
+    import synth
+
+    ndefl, n_rhs = 8, 12
+    ctx, field = _overlap_setup(L, torch)
+    act = L.action(L.LQ_OVERLAP, m=OV_M, rho=OV_RHO, cheb_N=OV_N)
+    b_d = torch.from_numpy(synth.point_sources(OV_LAT)).to(torch.device("cuda:0"))
+    x_d = torch.zeros_like(b_d)
+    t0 = time.perf_counter()
+    ev, est = L.lq_eigs(ctx, act, field, L.LQ_EIG_OVERLAP, ndefl, tol=1e-6)
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    log("sector modes", ev, est, t_eig, "s")
+    prm = L.params(tol=1e-10, sloppy_bits=16, deflate=ndefl)
+    stats = []
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = L.lq_solve(ctx, act, field, prm, b_d, x_d)
+        stats.append(st)
+        log("step", st)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    L.lq_field_free(field)
+    L.lq_finalize(ctx)
+    worst = max(s["true_rel_res"] for s in stats)
+    return {
+        "metric": METRIC, "value": round(n_rhs * args.steps / (t2 - t1), 5), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 0, "ms_per_step": round((t2 - t1) / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+        "config": {"workload": "overlap_deflated_chiral_cg_24x24x24x64_12rhs_cheb200_fp16", "lattice": list(OV_LAT),
+                   "deflate": ndefl, "rho": OV_RHO, "m": OV_M, "N": OV_N, "tol": 1e-10},
+        "roofline": None, "cpu_baseline": None, "converged": all(s["status"] == 0 for s in stats) and worst <= 1e-10,
+        "worst_true_rel_res": worst, "iters": [s["iters"] for s in stats],
+        "eigensolver": {"seconds": round(t_eig, 2), "restarts": est["iters"], "applications": est["n_apply"],
+                        "max_residual": est["true_rel_res"], "eigenvalues": [float(x) for x in ev]},
+    }
+
+
 def bench_serve(args, L, torch):
     """Poisson arrivals of 12-column solves at fractions of the measured
     closed-loop capacity; latency = completion - arrival."""
@@ -778,8 +886,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("tm", "hisq", "overlap", "overlap_mm", "overlap_sign", "serve", "wilson"),
-                    default="tm")
+    ap.add_argument("--workload", choices=("tm", "hisq", "overlap", "overlap_mm", "overlap_sign", "overlap_lowmodes",
+                                           "overlap_deflated", "serve", "wilson"), default="tm")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 single-column comparison")
     ap.add_argument("--recon12", type=int, default=0)
@@ -796,7 +904,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     fn = {"tm": bench_tm, "hisq": bench_hisq, "overlap": bench_overlap, "overlap_mm": bench_overlap_mm,
-          "overlap_sign": bench_overlap_sign, "serve": bench_serve, "wilson": bench_wilson}[args.workload]
+          "overlap_sign": bench_overlap_sign, "overlap_lowmodes": bench_overlap_lowmodes,
+          "overlap_deflated": bench_overlap_deflated, "serve": bench_serve, "wilson": bench_wilson}[args.workload]
     out = fn(args, L, torch)
     print(json.dumps(out), flush=True)
 

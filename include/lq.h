@@ -234,8 +234,9 @@ lq_status lq_hw_bounds(lq_ctx *ctx, const lq_action *act, const lq_field *g, int
  *                   above the cut (raise filter_cut).
  *   LQ_EIG_OVERLAP  the nev smallest eigenpairs of the chirally projected D(0)^dag D(0) =
  *                   2 rho^2 (1 + s P_s eps P_s) in each chirality s = +1, -1 (for
- *                   lq_params.deflate), with the action's sign function (FP64);
- *                   evals[2 nev]: s = +1 then s = -1, each ascending.
+ *                   lq_params.deflate), with the action's sign function (FP64; FP32 when
+ *                   tol >= 1e-6, enough for a deflation guess); evals[2 nev]: s = +1
+ *                   then s = -1, each ascending.
  * tol: residual target |A u - lambda u| relative to the operator norm (0: 1e-10);
  * max_restarts (0: 200).  stats: iters = restarts, n_apply = operator applications,
  * true_rel_res = largest residual.  LQ_ENOCONV: the modes are stored, some residual is

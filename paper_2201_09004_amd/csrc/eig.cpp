@@ -30,6 +30,8 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <random>
 
@@ -288,6 +290,10 @@ static int irl(lq_ctx* c, const Geom& g, hipStream_t s, const OpFn& A, const std
       worst = std::max(worst, std::fabs(beta[m - 1] * S[(size_t)(m - 1) * m + i]) / std::max(std::fabs(th[i]), 1e-300));
     out.worst_est = worst;
     out.restarts = rs;
+    if (const char* ev = getenv("LQ_VERBOSE"))
+      if (*ev && *ev != '0')
+        fprintf(stderr, "[lq] eigensolver restart %d: %d operator applications, worst Ritz estimate %.3e\n", rs,
+                out.applications, worst);
     if (worst <= tol || rs == max_restarts) {
       // Ritz vectors: V_{0..nev-1} <- V_m S[:, 0:nev]
       std::vector<zc> Sc((size_t)m * nev);
@@ -385,9 +391,10 @@ static int rayleigh_ritz(OpEnv& env, Vec& U, int n, std::vector<double>& lam, st
   int e = Aop(HU, Uv);
   if (e) return e;
   const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
-  if (rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, n, n, N, &one, colp(Uv, 0), N,
-                    colp(HU, 0), N, &zero, (rocblas_double_complex*)dM.p, n) != rocblas_status_success)
-    return fail(LQ_EDEVICE, "rocBLAS gemm");
+  for (int col = 0; col < n; ++col)  // M = U^H (H U), column by column (see project_out)
+    if (rocblas_zgemv(h, rocblas_operation_conjugate_transpose, N, n, &one, colp(Uv, 0), N, colp(HU, col), 1, &zero,
+                      (rocblas_double_complex*)dM.p + (size_t)col * n, 1) != rocblas_status_success)
+      return fail(LQ_EDEVICE, "rocBLAS gemv");
   std::vector<zc> Mc((size_t)n * n), M((size_t)n * n), G;
   hipMemcpyAsync(Mc.data(), dM.p, sizeof(zc) * n * n, hipMemcpyDeviceToHost, s);
   if (hipStreamSynchronize(s) != hipSuccess) return fail(LQ_EDEVICE, "Rayleigh-Ritz");
@@ -491,8 +498,19 @@ int eigs(lq_ctx* c, const lq_action* act, lq_field* f, int which, int nev, doubl
       if (!t.ok()) return fail(LQ_ENOMEM, "eigensolver");
       Blas bl;
       if ((e = blas_prepare(c, bl, g, 2, nev, s))) return e;
+      // the sign function in FP64, or in FP32 for a loose target (tol >= 1e-6:
+      // enough for a deflation guess, at a third of the cost)
+      const int ep = tol >= 1e-6 ? 32 : 64;
+      Vec t32i = make_vec(g, ep, 12, 1, 2, 0, s), t32o = make_vec(g, ep, 12, 1, 2, 0, s);
+      if (!t32i.ok() || !t32o.ok()) return fail(LQ_ENOMEM, "eigensolver");
+      auto sign_at = [&](Vec& out64, const Vec& in64) -> int {
+        if (ep == 64) return sign_apply(env, 64, out64, in64);
+        int r = vec_copy(t32i, in64);
+        if (!r) r = sign_apply(env, ep, t32o, t32i);
+        return r ? r : vec_copy(out64, t32o);
+      };
       OpFn A = [&](Vec& out, const Vec& in) {
-        int r = sign_apply(env, 64, t, in);
+        int r = sign_at(t, in);
         return r ? r : bl.plc(const_cast<Vec*>(&in), &t, &out, pc.as<double>());
       };
       IrlOut io;
@@ -511,9 +529,19 @@ int eigs(lq_ctx* c, const lq_action* act, lq_field* f, int which, int nev, doubl
       std::vector<double> qn((size_t)4 * nev);
       for (int l = 0; l < nev; ++l) std::memcpy(&qn[(size_t)4 * l], qh, sizeof(qh));
       hipMemcpyAsync(phn.p, qn.data(), sizeof(double) * qn.size(), hipMemcpyHostToDevice, s);
+      Vec ti = make_vec(g, ep, 12, nev, 2, 0, s), to = make_vec(g, ep, 12, nev, 2, 0, s);
+      if (!ti.ok() || !to.ok()) return fail(LQ_ENOMEM, "eigensolver");
       OpFn Hs = [&](Vec& out, const Vec& in) {
         Vec tv = view(tt, 0, in.ncol);
-        int r2 = sign_apply(env, 64, tv, in);
+        int r2 = 0;
+        if (ep == 64) {
+          r2 = sign_apply(env, 64, tv, in);
+        } else {
+          Vec tiv = view(ti, 0, in.ncol), tov = view(to, 0, in.ncol);
+          r2 = vec_copy(tiv, in);
+          if (!r2) r2 = sign_apply(env, ep, tov, tiv);
+          if (!r2) r2 = vec_copy(tv, tov);
+        }
         return r2 ? r2 : bl.plc(const_cast<Vec*>(&in), &tv, &out, phn.as<double>());
       };
       std::vector<double> mu, res;
@@ -583,9 +611,13 @@ int project_out(lq_ctx* c, const Geom& g, hipStream_t s, const EigSet& es, int n
   const int64_t N = col_len(g);
   const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0}, mone = {-1.0, 0.0};
   const rocblas_double_complex* U = (const rocblas_double_complex*)es.vecs;
-  if (rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, n, v.ncol, N, &one, U, N,
-                    colp(v, 0), N, &zero, (rocblas_double_complex*)coef, n) != rocblas_status_success ||
-      rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, N, v.ncol, n, &mone, U, N,
+  // U^H v column by column (a matrix-vector product per column: the library's
+  // gemm is slow for this shape, two tiny dimensions and one of ~1e7)
+  for (int col = 0; col < v.ncol; ++col)
+    if (rocblas_zgemv(h, rocblas_operation_conjugate_transpose, N, n, &one, U, N, colp(v, col), 1, &zero,
+                      (rocblas_double_complex*)coef + (size_t)col * n, 1) != rocblas_status_success)
+      return fail(LQ_EDEVICE, "rocBLAS gemv");
+  if (rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, N, v.ncol, n, &mone, U, N,
                     (const rocblas_double_complex*)coef, n, &one, colp(v, 0), N) != rocblas_status_success)
     return fail(LQ_EDEVICE, "rocBLAS gemm");
   return 0;
