@@ -98,6 +98,23 @@ class Engine {
   Clock::time_point last_used = Clock::now();
   std::vector<ColMeta> cols;
   std::unique_ptr<State> stp;  // per-column scalars of the Krylov recurrence
+  // iterations a column of this engine needs (running mean over finished
+  // columns; a first guess until one finishes), for the scheduler
+  double iters_per_col = 300.0;
+  int64_t finished_cols = 0;
+  void column_finished(int iters) {
+    ++finished_cols;
+    iters_per_col += (iters - iters_per_col) / (double)std::min<int64_t>(finished_cols, 32);
+  }
+  // device work of one iteration, in site-column units (a twisted-clover
+  // iteration is two Schur operators, about twice a HISQ one per site)
+  double iter_cost() const { return (double)g.Vh * std::max(w, 1) * (act.kind == LQ_HISQ ? 1.0 : 2.0); }
+  // work left: remaining iterations of the columns held, at this engine's cost per column-iteration
+  double remaining_work() const {
+    double it = 0.0;
+    for (int c = 0; c < w; ++c) it += std::max(1.0, iters_per_col - cols[c].iters);
+    return it * (double)g.Vh * (act.kind == LQ_HISQ ? 1.0 : 2.0);
+  }
   int plo = 32;
   double delta = 0.1;
   int maxiter = 10000;
@@ -288,6 +305,7 @@ class TmEngine : public Engine {
       Request* rq = m.req;
       rq->worst = std::max(rq->worst, res);
       rq->iters = std::max(rq->iters, m.iters);
+      column_finished(m.iters);
       if (res > tol) rq->status = LQ_ENOCONV;
       if (--rq->cols_left == 0) done.push_back(rq);
       const int last = w - 1;
@@ -456,6 +474,7 @@ class HisqEngine : public Engine {
       Request* rq = m.req;
       rq->worst = std::max(rq->worst, res);
       rq->iters = std::max(rq->iters, m.iters);
+      column_finished(m.iters);
       if (res > m.tol) rq->status = LQ_ENOCONV;
       if (--rq->cols_left == 0) done.push_back(rq);
       const int last = w - 1;
@@ -602,13 +621,32 @@ void worker_loop(ServerImpl& S) {
         rq->queued = false;
       }
     }
-    // one iteration of every engine: enqueue all, then complete (overlap on the device)
+    // One cycle: every engine with columns advances one iteration (all are
+    // enqueued first, so their kernels overlap on the device).  The engine
+    // with the least remaining work advances more iterations while the
+    // others' are in flight, about as many as fit in the costliest engine's
+    // iteration (at most 8): short requests finish in proportion to their
+    // own work instead of waiting one cycle of every engine per iteration.
     std::vector<Engine*> failed;
+    Engine* first = nullptr;
+    double cost_max = 0.0;
+    for (auto& e : S.engines) {
+      if (e->w == 0) continue;
+      cost_max = std::max(cost_max, e->iter_cost());
+      if (!first || e->remaining_work() < first->remaining_work()) first = e.get();
+    }
     for (auto& e : S.engines)
       if (e->w > 0 && e->step_enqueue()) failed.push_back(e.get());
     std::vector<Request*> done;
+    auto is_failed = [&](Engine* e) { return std::find(failed.begin(), failed.end(), e) != failed.end(); };
+    if (first && !is_failed(first)) {
+      int extra = std::min(8, (int)std::floor(cost_max / first->iter_cost())) - 1;
+      if (first->step_finish(done)) failed.push_back(first);
+      for (; extra > 0 && first->w > 0 && !is_failed(first); --extra)
+        if (first->step_enqueue() || first->step_finish(done)) failed.push_back(first);
+    }
     for (auto& e : S.engines) {
-      if (e->w == 0 || std::find(failed.begin(), failed.end(), e.get()) != failed.end()) continue;
+      if (e.get() == first || e->w == 0 || is_failed(e.get())) continue;
       if (e->step_finish(done)) failed.push_back(e.get());
     }
     {

@@ -124,3 +124,55 @@ def test_server_rejections(ctx):
         L.lq_server_destroy(tiny)
         L.lq_server_destroy(srv)
         L.lq_field_free(f)
+
+
+def test_budget_for_one_engine_makes_the_second_request_wait(ctx):
+    """With an HBM budget that holds one engine but not two, a request for a
+    second engine (another gauge field) waits until the first engine is idle
+    and evicted, then completes with the result it has alone."""
+    Lw = (4, 4, 4, 8)
+    Ua, Ub = synth.su3_field(Lw, 0.2, 95), synth.su3_field(Lw, 0.2, 96)
+    fa, fb = L.lq_gauge_load(ctx, Lw, Ua), L.lq_gauge_load(ctx, Lw, Ub)
+    tm = L.action(L.LQ_TM_CLOVER, m=M, mu=MU, c_sw=CSW)
+    prm = L.params(tol=1e-10, sloppy_bits=32)
+    b = np.ascontiguousarray(synth.point_sources(Lw)[:4])
+    srv = None
+    try:
+        # the smallest power-of-two budget that runs one engine: < 2 engines
+        budget = 1 << 16
+        while True:
+            probe = L.lq_server_create(ctx, budget, 4)
+            x = np.zeros_like(b)
+            t = L.lq_submit(probe, tm, fa, prm, b, x)
+            try:
+                L.lq_wait(probe, t)
+                ok = True
+            except L.LqError as e:
+                assert e.code == L.LQ_ENOMEM
+                ok = False
+            L.lq_server_destroy(probe)
+            if ok:
+                break
+            budget *= 2
+            assert budget < (1 << 34)
+        srv = L.lq_server_create(ctx, budget, 4)
+        xa, xb = np.zeros_like(b), np.zeros_like(b)
+        sa, sb = L.lq_stats(), L.lq_stats()
+        ta = L.lq_submit(srv, tm, fa, prm, b, xa, sa)
+        tb = L.lq_submit(srv, tm, fb, prm, b, xb, sb)
+        L.lq_wait(srv, ta)
+        L.lq_wait(srv, tb)
+        da, db = sa.as_dict(), sb.as_dict()
+        assert da["status"] == 0 and db["status"] == 0
+        # b waited for a: its latency covers a's solve and its own
+        assert db["seconds"] > da["seconds"]
+        for U, f, x in ((Ua, fa, xa), (Ub, fb, xb)):
+            F = W.field_strength(U)
+            assert _resid(lambda v: W.tm_clover(U, v, M, CSW, MU, F=F), x, b) < 1e-10
+            alone, st = L.lq_solve(ctx, tm, f, prm, b)
+            assert rel(x, alone) < 1e-8
+    finally:
+        if srv is not None:
+            L.lq_server_destroy(srv)
+        L.lq_field_free(fa)
+        L.lq_field_free(fb)
