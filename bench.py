@@ -93,7 +93,29 @@ def profile_table(L, ctx, names):
         n, avg = L.lq_profile_get(ctx, name)
         if n:
             out[name] = {"count": n, "avg_ms": avg, "total_ms": n * avg}
+            b = L.lq_profile_bytes(ctx, name)
+            if b > 0:
+                out[name]["alg_bytes"] = b
+                out[name]["alg_gbs"] = round(b / (n * avg * 1e-3) / 1e9, 1)
     return out
+
+
+BLAS_OPS = ["axpy", "axmy", "xpay", "cg", "bicg_xr", "bicg_p", "dot", "norm2", "dot_norm", "xmy_norm", "zero",
+            "scale", "g5", "lc_g5", "copy", "plc"]
+
+
+def family_roofline(kernels, families):
+    """Roofline of the family (one kernel, all its launch widths) with the most
+    time: its algorithmic bytes over its total time, i.e. the average bytes of
+    a launch over the average launch duration."""
+    fam = {k: kernels[k] for k in families if k in kernels and kernels[k].get("alg_bytes")}
+    dom = max(fam, key=lambda k: fam[k]["total_ms"])
+    f = fam[dom]
+    achieved = f["alg_bytes"] / (f["total_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "alg_bytes_per_launch": f["alg_bytes"] / f["count"], "avg_ms": f["avg_ms"], "launches": f["count"],
+            "share_of_step": None}
 
 
 # Sources that define the stencil kernels; measured HBM traffic is reported
@@ -433,18 +455,19 @@ def bench_hisq(args, L, torch):
     ms_step = (t1 - t0) / args.steps * 1e3
     value = n_rhs * args.steps / (t1 - t0)
     worst = max(s["true_rel_res"] for s in stats)
-    names = [f"stag{p}_{e}" for p in (16, 32, 64) for e in ("hop", "xpay")]
-    kernels = profile_table(L, ctx, names + [f"{k}_n{n_rhs}" for k in names] + ["blas"])
+    names = [f"stag{p}_{e}" for p in (16, 32, 64) for e in ("hop", "xpay", "xpayd")]
+    vec_names = [f"blas{p}_{o}" for p in (16, 32, 64) for o in BLAS_OPS] + [f"ms{p}_{k}" for p in (16, 32)
+                                                                             for k in ("xr", "p")]
+    kernels = profile_table(L, ctx, names + [f"{k}_n{n_rhs}" for k in names] + vec_names + ["blas"])
     L.lq_profile(ctx, False)
-    Vh = int(np.prod(HISQ_LAT)) // 2
-    # roofline from the 12-column launches of the sloppy stencils (the FP32
-    # multi-shift stage; the FP16 refinement launches run at other widths)
-    wide = [k for k in kernels if k.startswith(("stag16", "stag32")) and k.endswith(f"_n{n_rhs}")]
-    dom_n = max(wide, key=lambda k: kernels[k]["total_ms"])
-    dom = dom_n[: -len(f"_n{n_rhs}")]
-    roof = roofline_for({dom: kernels[dom_n]}, dom, stag_site_bytes(int(dom[4:6]), dom.split("_")[1], n_rhs) * Vh,
-                        measured_traffic(dom, "hisq_multishift_cg_32x32x32x96_12rhs_8mass"))
-    roof["launches_at_12_columns"] = kernels[dom_n]["count"]
+    # roofline of the kernel family (all launch widths) with the most time in
+    # the step: the FP16 refinement stencils, the FP32 multi-shift stencils or
+    # one of the vector kernels
+    roof = family_roofline(kernels, names + vec_names)
+    roof["share_of_step"] = round(kernels[roof["kernel"]]["total_ms"] / (ms_step * args.steps), 4)
+    step_ms = ms_step * args.steps
+    shares = {"stencils": round(sum(kernels[k]["total_ms"] for k in names if k in kernels) / step_ms, 3),
+              "vector_kernels": round(kernels["blas"]["total_ms"] / step_ms, 3) if "blas" in kernels else None}
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline")
@@ -460,6 +483,7 @@ def bench_hisq(args, L, torch):
                    "n_rhs": n_rhs, "masses": HISQ_MASSES,
                    "sloppy": "fp32 multi-shift, fp16 refinement, fp64 reliable", "tol": 1e-10},
         "roofline": roof, "cpu_baseline": cpu, "worst_true_rel_res": worst,
+        "time_shares": shares,
         "mass_columns_per_s": round(value * len(HISQ_MASSES), 3),
         "iters": [s["iters"] for s in stats], "kernels": kernels,
     }
@@ -825,51 +849,92 @@ def bench_serve(args, L, torch):
     kinds = [(lat, kind) for lat in sizes for kind in ("tm", "hisq")]
     rng = np.random.default_rng(3005)
 
-    def run(n_req, rate):
+    # Solutions are host arrays of 12 columns (4.8 GB for a 32^3x64 twisted-
+    # clover request): a finished request's solution is dropped at once, and a
+    # new one is submitted only while the solutions in flight stay under
+    # HOST_INFLIGHT_BYTES (the closed loop keeps at most that much queued; in the
+    # open loop a held-back arrival counts its wait in its latency).
+    HOST_INFLIGHT_BYTES = 96e9
+
+    def run(n_req, rate, tag):
         srv = L.lq_server_create(ctx, 0, 24)
         order = [kinds[i] for i in rng.integers(0, len(kinds), n_req)]
-        reqs = []
+        reqs = []  # [ticket, stats, solution or None, key, arrival time, submit time, completion time]
+        n_done = 0
+        inflight = 0
+
+        def collect(block_one):
+            nonlocal n_done, inflight
+            for r in reqs:
+                if r[2] is None:
+                    continue
+                if block_one:
+                    L.lq_wait(srv, r[0])
+                    block_one = False
+                elif not L.lq_poll(srv, r[0]):
+                    continue
+                r[6] = time.perf_counter()
+                inflight -= r[2].nbytes
+                r[2] = None
+                n_done += 1
+                if n_done % 16 == 0 or n_done == n_req:
+                    log(f"{tag}: {n_done}/{n_req} requests done, {time.perf_counter() - t_start:.0f} s")
+
         t_start = time.perf_counter()
-        t_next = t_start
+        t_arr = t_start
         for key in order:
             if rate:
-                t_next += rng.exponential(1.0 / rate)
-                d = t_next - time.perf_counter()
+                t_arr += rng.exponential(1.0 / rate)
+                d = t_arr - time.perf_counter()
                 if d > 0:
                     time.sleep(d)
             b = sources[key]
+            while inflight > 0 and inflight + b.nbytes > HOST_INFLIGHT_BYTES:
+                collect(True)
             x = np.zeros_like(b)
             st = L.lq_stats()
             act, prm = (tm, p_tm) if key[1] == "tm" else (hq, p_hq)
+            t_sub = time.perf_counter()
             t = L.lq_submit(srv, act, fields[key], prm, b, x, st)
-            reqs.append((t, st, b, x, key))
-        for t, *_ in reqs:
-            L.lq_wait(srv, t)
+            inflight += x.nbytes
+            reqs.append([t, st, x, key, t_arr if rate else t_start, t_sub, None])
+            collect(False)
+        while n_done < n_req:
+            collect(True)
         span = time.perf_counter() - t_start
-        lat = np.array([st.seconds for _, st, *_ in reqs])
-        ok = all(st.status == 0 for _, st, *_ in reqs)
+        # latency from arrival: the server's submit-to-completion time plus any
+        # wait for host memory before the submission
+        lat = np.array([r[1].seconds + (r[5] - r[4]) for r in reqs])
+        ok = all(r[1].status == 0 for r in reqs)
         L.lq_server_destroy(srv)
+        by_kind = {}
+        for r, l in zip(reqs, lat):
+            by_kind.setdefault(f"{'x'.join(map(str, r[3][0]))}_{r[3][1]}", []).append(l)
         return {"requests": n_req, "rate_req_per_s": rate, "span_s": span, "req_per_s": n_req / span,
                 "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-                "all_converged": ok}
+                "all_converged": ok,
+                "p50_by_kind_s": {k: round(float(np.percentile(v, 50)), 3) for k, v in sorted(by_kind.items())}}
 
     log("warm engines")
-    run(len(kinds), 0)
-    log("closed loop")
-    closed = run(args.serve_requests, 0)
+    run(len(kinds), 0, "warm")
+    if args.serve_capacity > 0:
+        closed = {"req_per_s": args.serve_capacity, "given": True}
+    else:
+        log("closed loop")
+        closed = run(args.serve_requests, 0, "closed")
     mu_max = closed["req_per_s"]
     log("capacity", mu_max, "req/s")
     open_loop = []
-    for f in (0.5, 0.8, 0.95):
+    for f in [float(v) for v in args.serve_rates.split(",") if v]:
         log("rate", f)
-        r = run(args.serve_requests, f * mu_max)
+        r = run(args.serve_requests, f * mu_max, f"rate {f}")
         r["fraction"] = f
         open_loop.append(r)
         log(r)
     for f in fields.values():
         L.lq_field_free(f)
     L.lq_finalize(ctx)
-    worst = open_loop[-1]
+    worst = open_loop[-1] if open_loop else closed
     return {
         "metric": METRIC, "value": round(closed["req_per_s"] * 12, 4), "unit": "solves/s", "n_gpus": 1,
         "steps": args.serve_requests, "warmup": len(kinds), "ms_per_step": round(1e3 / closed["req_per_s"], 3),
@@ -877,7 +942,7 @@ def bench_serve(args, L, torch):
         "config": {"workload": "serve_mixed_tm_hisq_16x32_24x64_32x64_12rhs", "sizes": [list(s) for s in sizes],
                    "actions": ["tm_clover fp32", "hisq m=0.01 fp16"], "max_cols": 24},
         "roofline": None, "cpu_baseline": None,
-        "closed_loop": closed, "poisson": open_loop, "p50_s": worst["p50_s"], "p99_s": worst["p99_s"],
+        "closed_loop": closed, "poisson": open_loop, "p50_s": worst.get("p50_s"), "p99_s": worst.get("p99_s"),
     }
 
 
@@ -891,7 +956,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 single-column comparison")
     ap.add_argument("--recon12", type=int, default=0)
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=256, help="requests per arrival rate (serve)")
+    ap.add_argument("--serve-rates", default="0.5,0.8,0.95", help="arrival rates as fractions of capacity (serve)")
+    ap.add_argument("--serve-capacity", type=float, default=0.0,
+                    help="closed-loop capacity in requests/s from an earlier run (serve; 0: measure it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "

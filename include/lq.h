@@ -124,7 +124,9 @@ typedef struct {
   int32_t use_initial_guess;/* 1: x holds the initial guess on input */
   int32_t fault_inject;    /* testing: 1 NaN in the first reduction, 2 allocation failure, 3 maxiter=1 */
   int32_t solver;          /* 0: default for the action, 1: CG on normal equations D^dag D (full lattice,
-                              twisted clover and overlap) */
+                              twisted clover and overlap), 2: twisted clover even-odd flexible GCR(8)
+                              in FP64, each direction from a sloppy BiCGStab to 0.1 of the residual
+                              (at most 50 iterations), restarted from the true residual */
   int32_t deflate;         /* overlap (solver 0): use this many resident chiral-sector low modes per
                               chirality (lq_eigs with LQ_EIG_OVERLAP) for the initial guess of every
                               sector solve; 0: none */
@@ -262,6 +264,13 @@ lq_status lq_copy_bandwidth(lq_ctx *ctx, size_t bytes, int reps, double *gbs);
  * average duration in milliseconds. */
 lq_status lq_profile(lq_ctx *ctx, int enable);
 lq_status lq_profile_get(lq_ctx *ctx, const char *name, int64_t *count, double *avg_ms);
+/* Algorithmic bytes (every operand read once, every output written once) of
+ * the launches timed under `name` since profiling was enabled.  Names: the
+ * stencil kernels as above (wilson32_clovinv, stag16_xpayd, ... and their
+ * _n<columns> forms), "blas<prec>_<op>" (axpy, cg, xpay, dot, bicg_xr, ...),
+ * "ms<prec>_xr" and "ms<prec>_p" (multi-shift vector kernels) and "blas" for
+ * all vector kernels together. */
+lq_status lq_profile_bytes(lq_ctx *ctx, const char *name, double *bytes);
 
 /* Serving: continuous batching of propagator solves (the 12 spin-colour
  * columns of sec. 2.1, the colour columns of sec. 2.2) on resident gauge

@@ -267,6 +267,9 @@ static int check_solve(lq_ctx* c, const lq_action* act, const lq_field* g, const
   if (prm->n_shift < 0 || prm->n_shift > 64) return fail(LQ_EINVAL, "n_shift out of range");
   if (prm->n_shift > 1 && act->kind != LQ_HISQ && act->kind != LQ_OVERLAP)
     return fail(LQ_EINVAL, "several masses are implemented for HISQ and overlap");
+  if (prm->solver < 0 || prm->solver > 2) return fail(LQ_EINVAL, "solver must be 0, 1 or 2");
+  if (prm->solver == 2 && act->kind != LQ_TM_CLOVER)
+    return fail(LQ_EINVAL, "solver 2 (flexible GCR) is implemented for the twisted-clover action");
   if (prm->n_shift > 1 && act->kind == LQ_OVERLAP && prm->solver == 1)
     return fail(LQ_EINVAL, "overlap: several masses need the chirally projected solver (solver = 0)");
   return 0;
@@ -379,8 +382,20 @@ lq_status lq_profile(lq_ctx* c, int enable) {
   if (!c) return (lq_status)fail(LQ_EINVAL, "ctx is NULL");
   std::lock_guard<std::recursive_mutex> lk(c->prof_mtx);
   prof_flush(c);
-  if (enable) c->totals.clear();
+  if (enable) {
+    c->totals.clear();
+    c->byte_totals.clear();
+  }
   c->prof = enable != 0;
+  return LQ_OK;
+}
+
+lq_status lq_profile_bytes(lq_ctx* c, const char* name, double* bytes) {
+  if (!c || !name || !bytes) return (lq_status)fail(LQ_EINVAL, "NULL argument");
+  std::lock_guard<std::recursive_mutex> lk(c->prof_mtx);
+  prof_flush(c);
+  auto it = c->byte_totals.find(name);
+  *bytes = it == c->byte_totals.end() ? 0.0 : it->second;
   return LQ_OK;
 }
 

@@ -27,6 +27,7 @@ inline int pidx(int prec) { return prec == 64 ? 0 : prec == 32 ? 1 : 2; }
 struct ProfRec {
   std::string name;
   hipEvent_t a, b;
+  double bytes;  // algorithmic bytes of the work timed
 };
 
 // tuned launch shape of a stencil kernel
@@ -46,6 +47,7 @@ struct lq_ctx {
   std::vector<lq::ProfRec> pending;
   std::vector<hipEvent_t> event_pool;
   std::map<std::string, std::pair<int64_t, double>> totals;
+  std::map<std::string, double> byte_totals;  // algorithmic bytes per timed name
   void* scratch = nullptr;    // this device's address of the allocation-free entry point's scratch
   void* rocblas = nullptr;    // rocBLAS handle of the eigensolver (created on first use)
   double* partial = nullptr;  // reduction partials
@@ -110,7 +112,7 @@ struct Prof {
   hipStream_t s;
   bool on = false;
   ProfRec rec;
-  Prof(lq_ctx* ctx, const char* name, hipStream_t st);
+  Prof(lq_ctx* ctx, const char* name, hipStream_t st, double bytes = 0.0);
   ~Prof();
   Prof(const Prof&) = delete;
   Prof& operator=(const Prof&) = delete;
@@ -206,7 +208,10 @@ int overlap_prepare(OpEnv& e);
 // staggered
 int stag_D(OpEnv& e, int prec, Vec& out, const Vec& in, bool dag, const double* acol_dev = nullptr);
 int stag_hop(OpEnv& e, int prec, Vec& out, const Vec& in);
-int stag_normal_even(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o, const double* acol_dev, double a);
+// red: if not null, <in_e, out_e> per column as partials over 64-site tiles
+// ([col][tile][4], re and im in the first two) from the second stencil's epilogue
+int stag_normal_even(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o, const double* acol_dev, double a,
+                     double* red = nullptr);
 
 // ------------------------------------------------------------------ BLAS helpers
 struct Blas {
@@ -246,5 +251,6 @@ int project_out(lq_ctx* c, const Geom& g, hipStream_t s, const EigSet& es, int n
 int add_modes(lq_ctx* c, const Geom& g, hipStream_t s, const EigSet& es, int n, const std::vector<double>& w,
               Vec& v, void* coef);
 void eig_release(lq_ctx* c);
+
 
 }  // namespace lq

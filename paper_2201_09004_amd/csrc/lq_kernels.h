@@ -42,7 +42,10 @@ int launch_site(const Geom& g, int prec, const void* clov, const void* clov_inv,
                 FieldRef in, FieldRef out, int par_out, int ncol, hipStream_t s);
 
 // ------------------------------------------------------------ staggered
-enum { SEPI_HOP = 0, SEPI_XPAY };
+// SEPI_XPAY_DOT: SEPI_XPAY plus the per-column <x, out> written as wave
+// partials red[(col * ntile + tile) * 4 + {0: re, 1: im}] (ntile = 64-site
+// tiles of the launch)
+enum { SEPI_HOP = 0, SEPI_XPAY, SEPI_XPAY_DOT };
 
 struct StagArgs {
   Geom g;
@@ -57,6 +60,7 @@ struct StagArgs {
   FieldRef in, out, x;
   const double* acol;
   double a, k_hop;
+  double* red;  // SEPI_XPAY_DOT partials
 };
 int launch_stag(const StagArgs& A, hipStream_t s);
 

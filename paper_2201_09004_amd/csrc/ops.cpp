@@ -12,7 +12,7 @@
 namespace lq {
 
 // ------------------------------------------------------------------ timing
-Prof::Prof(lq_ctx* ctx, const char* name, hipStream_t st) : c(ctx), s(st) {
+Prof::Prof(lq_ctx* ctx, const char* name, hipStream_t st, double bytes) : c(ctx), s(st) {
   if (!c || !c->prof) return;
   std::lock_guard<std::recursive_mutex> lk(c->prof_mtx);
   hipEvent_t ev[2];
@@ -26,7 +26,7 @@ Prof::Prof(lq_ctx* ctx, const char* name, hipStream_t st) : c(ctx), s(st) {
       return;
     }
   }
-  rec = {name, ev[0], ev[1]};
+  rec = {name, ev[0], ev[1], bytes};
   on = hipEventRecord(ev[0], s) == hipSuccess;
   if (!on) {
     (void)hipGetLastError();
@@ -55,11 +55,40 @@ void prof_flush(lq_ctx* c) {
     auto& t = c->totals[r.name];
     t.first += 1;
     t.second += ms;
+    c->byte_totals[r.name] += r.bytes;
     c->event_pool.push_back(r.a);
     c->event_pool.push_back(r.b);
   }
   c->pending.clear();
 }
+
+// field transfers of one BLAS op per site and column (each operand read
+// once, each result written once): its algorithmic bytes for the timing records
+static int blas_transfers(int op) {
+  switch (op) {
+    case OP_AXPY: case OP_AXMY: case OP_XPAY: case OP_XMY_NORM: case OP_LC_G5: case OP_PLC: return 3;
+    case OP_CG: return 6;
+    case OP_BICG_XR: return 7;
+    case OP_BICG_P: return 4;
+    case OP_DOT: case OP_DOT_NORM: case OP_SCALE: case OP_G5: case OP_COPY: return 2;
+    default: return 1;
+  }
+}
+static const char* blas_name(int op) {
+  static const char* n[] = {"axpy", "axmy", "xpay", "cg", "bicg_xr", "bicg_p", "dot", "norm2", "dot_norm",
+                            "xmy_norm", "zero", "scale", "g5", "lc_g5", "copy", "plc"};
+  return op >= 0 && op < OP_NCOUNT ? n[op] : "op";
+}
+struct BlasProf {
+  Prof all, one;
+  char name[48];
+  static double bytes(const BlasArgs& A) {
+    return (double)A.ncol * A.npar * A.Vh * blas_transfers(A.op) * (site_bytes(A.prec, A.nc) + (A.prec == 16 ? 4 : 0));
+  }
+  BlasProf(lq_ctx* c, const BlasArgs& A, hipStream_t s)
+      : all(c, "blas", s, bytes(A)), one(c, (snprintf(name, sizeof(name), "blas%d_%s", A.prec, blas_name(A.op)), name),
+                                         s, bytes(A)) {}
+};
 
 // ------------------------------------------------------------------ vectors
 static size_t block_bytes(int prec, int nc, int Vh) { return (size_t)site_bytes(prec, nc) * Vh; }
@@ -486,15 +515,16 @@ static int run_wilson(OpEnv& e, WilsonArgs& A, int n_fields, int clov_mats, int 
   // converged columns launch the same kernel at several widths)
   char name_n[64];
   snprintf(name_n, sizeof(name_n), "%s_n%d", name, A.ncol);
-  Prof p(e.noalloc ? nullptr : e.ctx, name, e.s);
-  Prof pn(e.noalloc ? nullptr : e.ctx, name_n, e.s);
+  const double launch_bytes = (double)nsite * wilson_bytes(A.prec, A.recon, n_fields, A.ncol, clov_mats);
+  Prof p(e.noalloc ? nullptr : e.ctx, name, e.s, launch_bytes);
+  Prof pn(e.noalloc ? nullptr : e.ctx, name_n, e.s, launch_bytes);
   int r = tuned(e.ctx, key, A, tune_out_bytes(A.prec, 12, A.ncol, out_npar, A.g.Vh), A.prec,
                 nr_candidates(A.prec, A.ncol, blocked), e.s,
                 [](const WilsonArgs& B, hipStream_t st) { return launch_wilson(B, st); }, !e.noalloc);
   if (r) return fail(r == -1 ? LQ_ENOTSUP : LQ_EDEVICE, "wilson stencil launch");
   e.n_apply += A.par_out == 2 ? 2 : 1;
   e.flops += (double)nsite * A.ncol * (1320.0 + flops_extra);
-  e.bytes += (double)nsite * wilson_bytes(A.prec, A.recon, n_fields, A.ncol, clov_mats);
+  e.bytes += launch_bytes;
   return 0;
 }
 
@@ -773,7 +803,7 @@ static int sign_poly(OpEnv& e, int prec, Vec& out, const Vec& in) {
     BlasArgs B{};
     B.prec = prec; B.nc = 12; B.ncol = in.ncol; B.npar = 2; B.Vh = g.Vh; B.op = OP_LC_G5;
     B.f[0] = in.f; B.f[1] = in.f; B.f[2] = bk1.f; B.imm[0] = e.cheb[N]; B.gridx = bl.gridx;
-    Prof p(e.ctx, "blas", e.s);
+    BlasProf p(e.ctx, B, e.s);
     if (launch_blas(B, e.s)) return fail(LQ_EDEVICE, "blas");
   }
   if ((r = vec_zero(bk2))) return fail(LQ_EDEVICE, "zero");
@@ -866,7 +896,7 @@ int overlap_D(OpEnv& e, int prec, Vec& out, const Vec& in, bool dag) {
   B.imm[0] = rho + 0.5 * m;
   B.imm[2] = rho - 0.5 * m;
   {
-    Prof p(e.ctx, "blas", e.s);
+    BlasProf p(e.ctx, B, e.s);
     if (launch_blas(B, e.s)) return fail(LQ_EDEVICE, "blas");
   }
   if (dag) return bl.op(OP_G5, &ein, &out);
@@ -884,7 +914,7 @@ static int run_stag(OpEnv& e, StagArgs& A, int n_fields) {
   A.slong = e.f->slng[pi];
   const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
   char name[48];
-  snprintf(name, sizeof(name), "stag%d_%s", A.prec, A.epi == SEPI_HOP ? "hop" : "xpay");
+  snprintf(name, sizeof(name), "stag%d_%s", A.prec, A.epi == SEPI_HOP ? "hop" : A.epi == SEPI_XPAY ? "xpay" : "xpayd");
   char key[160];
   snprintf(key, sizeof(key), "%s_n%d_v%d_p%d", name, col_bucket(A.ncol), A.g.Vh, A.par_out);
   std::vector<int> nrs{1};
@@ -894,15 +924,17 @@ static int run_stag(OpEnv& e, StagArgs& A, int n_fields) {
   // converged columns launch the same kernel at several widths)
   char name_n[64];
   snprintf(name_n, sizeof(name_n), "%s_n%d", name, A.ncol);
-  Prof p(e.noalloc ? nullptr : e.ctx, name, e.s);
-  Prof pn(e.noalloc ? nullptr : e.ctx, name_n, e.s);
+  const double rb = A.prec == 64 ? 8 : A.prec == 32 ? 4 : 2;
+  const double launch_bytes =
+      (double)nsite * (16 * 18 * rb + (double)A.ncol * n_fields * (6 * rb + (A.prec == 16 ? 4 : 0)));
+  Prof p(e.noalloc ? nullptr : e.ctx, name, e.s, launch_bytes);
+  Prof pn(e.noalloc ? nullptr : e.ctx, name_n, e.s, launch_bytes);
   if (tuned(e.ctx, key, A, tune_out_bytes(A.prec, 3, A.ncol, A.out.npar, A.g.Vh), A.prec, nrs, e.s,
             [](const StagArgs& B, hipStream_t st) { return launch_stag(B, st); }, !e.noalloc))
     return fail(LQ_EDEVICE, "staggered stencil launch");
   e.n_apply += A.par_out == 2 ? 2 : 1;
-  const double rb = A.prec == 64 ? 8 : A.prec == 32 ? 4 : 2;
   e.flops += (double)nsite * A.ncol * 1146.0;
-  e.bytes += (double)nsite * (16 * 18 * rb + (double)A.ncol * n_fields * (6 * rb + (A.prec == 16 ? 4 : 0)));
+  e.bytes += launch_bytes;
   return 0;
 }
 
@@ -937,7 +969,8 @@ int stag_hop(OpEnv& e, int prec, Vec& out, const Vec& in) {
   return run_stag(e, A, 2);
 }
 
-int stag_normal_even(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o, const double* acol_dev, double a) {
+int stag_normal_even(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o, const double* acol_dev, double a,
+                     double* red) {
   int r = ensure_links(e, prec);
   if (r) return r;
   StagArgs A{};
@@ -957,6 +990,10 @@ int stag_normal_even(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o
   A.acol = acol_dev;
   A.a = a;
   A.k_hop = -1.0;
+  if (red) {
+    A.epi = SEPI_XPAY_DOT;
+    A.red = red;
+  }
   return run_stag(e, A, 3);
 }
 
@@ -992,7 +1029,7 @@ int Blas::op(int opc, Vec* f0, Vec* f1, Vec* f2, Vec* f3, Vec* f4, const double*
   A.c1 = c1;
   A.partial = partial;
   A.gridx = gridx;
-  Prof p(ctx, "blas", s);
+  BlasProf p(ctx, A, s);
   return launch_blas(A, s) ? fail(LQ_EDEVICE, "blas launch") : 0;
 }
 
@@ -1013,7 +1050,7 @@ int Blas::opi(int opc, Vec* f0, Vec* f1, Vec* f2, double c0re, double c0im, doub
   A.imm[3] = c1im;
   A.partial = partial;
   A.gridx = gridx;
-  Prof p(ctx, "blas", s);
+  BlasProf p(ctx, A, s);
   return launch_blas(A, s) ? fail(LQ_EDEVICE, "blas launch") : 0;
 }
 
@@ -1034,7 +1071,7 @@ int Blas::plc(Vec* f0, Vec* f1, Vec* f2, const double* pcol) {
   A.pcol = pcol;
   A.partial = partial;
   A.gridx = gridx;
-  Prof p(ctx, "blas", s);
+  BlasProf p(ctx, A, s);
   return launch_blas(A, s) ? fail(LQ_EDEVICE, "blas launch") : 0;
 }
 

@@ -40,6 +40,22 @@ static bool verbose() {
   return v;
 }
 
+// timing records of the multi-shift vector kernels with their algorithmic
+// bytes: ms_xr reads r and A p and writes r (base columns); ms_p reads r once
+// and, per shift column, reads p and x and writes both
+struct MsProf {
+  Prof all, one;
+  char name[32];
+  static double bytes(const MsArgs& M, bool p) {
+    const double sb = (double)site_bytes(M.prec, M.nc) + (M.prec == 16 ? 4 : 0);
+    const double cols = p ? M.nrhs + 4.0 * M.nshift * M.nrhs : 3.0 * M.nrhs;
+    return cols * M.npar * M.Vh * sb;
+  }
+  MsProf(lq_ctx* c, const MsArgs& M, bool p, hipStream_t s)
+      : all(c, "blas", s, bytes(M, p)),
+        one(c, (snprintf(name, sizeof(name), "ms%d_%s", M.prec, p ? "p" : "xr"), name), s, bytes(M, p)) {}
+};
+
 namespace {
 struct Counters {
   int iters = 0, reliable = 0, restarts = 0;
@@ -145,6 +161,10 @@ struct Compactor {
   }
 };
 
+// A sloppy operator that also returns reductions as partials over 64-site
+// tiles ([col][tile][4]): mode 1 <in, out> (CG), mode 2 <out, in> and |out|^2 (BiCGStab)
+using FusedFn = std::function<int(Vec& out, const Vec& in, int mode, double* red)>;
+
 // Mixed-precision CG with reliable updates on a Hermitian positive-definite A.
 // x, b: FP64.  Columns stop when the FP64 residual of A meets tol[c] |b_c|.
 // Converged columns are moved behind the active ones (columns of every
@@ -153,9 +173,14 @@ struct Compactor {
 // are put back in their original order before returning.  A_hi and A_lo
 // receive views of the active columns.
 int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int plo, Vec& x, Vec& b,
-             const std::vector<double>& tol_in, int maxiter, double delta, Counters& cnt, ColParam* cp = nullptr) {
+             const std::vector<double>& tol_in, int maxiter, double delta, Counters& cnt, ColParam* cp = nullptr,
+             const FusedFn* A_fused = nullptr) {
   const int n = b.ncol, nc = b.nc, npar = b.npar, par0 = b.par0;
   hipStream_t s = bl.s;
+  // A_fused: the sloppy operator with <p, A p> from its stencil epilogue
+  const int fused_tiles = (npar * g.Vh + 63) / 64;
+  DBuf redbuf(A_fused ? sizeof(double) * 4 * (size_t)fused_tiles * n : 0, s);
+  if (A_fused && !redbuf.p) return fail(LQ_ENOMEM, "reduction partials");
   Vec r = make_vec(g, 64, nc, n, npar, par0, s);
   Vec q64 = make_vec(g, 64, nc, n, npar, par0, s);
   Vec rs = make_vec(g, plo, nc, n, npar, par0, s);
@@ -209,9 +234,15 @@ int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int pl
   int it = 0;
   for (; it < maxiter && na > 0; ++it) {
     Vec pv = view(p, 0, na), qv = view(q, 0, na), xsv = view(xs, 0, na), rsv = view(rs, 0, na);
-    if ((e = A_lo(qv, pv))) return e;
-    if ((e = bl.op(OP_DOT, &pv, &qv))) return e;
-    if (launch_scalar(SC_CG_ALPHA, bl.partial, bl.gridx, na, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    if (A_fused) {
+      if ((e = (*A_fused)(qv, pv, 1, redbuf.as<double>()))) return e;
+      if (launch_scalar(SC_CG_ALPHA, redbuf.as<double>(), fused_tiles, na, st.d(), s))
+        return fail(LQ_EDEVICE, "scalar");
+    } else {
+      if ((e = A_lo(qv, pv))) return e;
+      if ((e = bl.op(OP_DOT, &pv, &qv))) return e;
+      if (launch_scalar(SC_CG_ALPHA, bl.partial, bl.gridx, na, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+    }
     if ((e = bl.op(OP_CG, &pv, &qv, &xsv, &rsv, nullptr, st.d(), ST_ALPHA, ST_ALPHA))) return e;
     if (launch_scalar(SC_CG_BETA, bl.partial, bl.gridx, na, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
     ++since;
@@ -299,7 +330,6 @@ int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int pl
 // Mixed-precision BiCGStab with reliable updates for a non-Hermitian M.
 // M_fused (optional): the sloppy operator with the fused reductions <out, in>
 // and |out|^2 (mode 2) as partials over 64-site tiles.
-using FusedFn = std::function<int(Vec& out, const Vec& in, int mode, double* red)>;
 
 int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int plo, Vec& x, Vec& b,
                    const std::vector<double>& tol_in, int maxiter, double delta, Counters& cnt,
@@ -459,6 +489,111 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
   if ((e = cm.restore())) return e;
   cnt.iters += it;
   return left > 0 ? LQ_ENOCONV : LQ_OK;
+}
+
+// Flexible GCR (generalised conjugate residual, restarted after kmax
+// directions) in FP64 on a non-Hermitian M, preconditioned by a short sloppy
+// BiCGStab solve of M z = r (to `inner_tol` relative to r, at most
+// `inner_iters` iterations): every outer direction z_k = P(r) may come from a
+// different preconditioner, so M z_k is orthogonalised against the earlier
+// M z_j (modified Gram-Schmidt, applied to z_k alike) and the residual is
+// minimised over the span.  The outer recurrence is FP64, so r stays the
+// true residual up to rounding; it is recomputed at every restart.
+int gcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int plo, Vec& x, Vec& b,
+              const std::vector<double>& tol_in, int maxiter, double delta, Counters& cnt, const FusedFn* M_fused,
+              int kmax, double inner_tol, int inner_iters) {
+  const int n = b.ncol, nc = b.nc, npar = b.npar, par0 = b.par0;
+  hipStream_t s = bl.s;
+  Vec r = make_vec(g, 64, nc, n, npar, par0, s), q = make_vec(g, 64, nc, n, npar, par0, s);
+  std::vector<Vec> Z, W;
+  for (int k = 0; k < kmax; ++k) {
+    Z.push_back(make_vec(g, 64, nc, n, npar, par0, s));
+    W.push_back(make_vec(g, 64, nc, n, npar, par0, s));
+    if (!Z.back().ok() || !W.back().ok()) return fail(LQ_ENOMEM, "gcr buffers");
+  }
+  State st(n, s);
+  if (!r.ok() || !q.ok() || !st.ok()) return fail(LQ_ENOMEM, "gcr buffers");
+  for (int c = 0; c < n; ++c) {
+    for (int k = 0; k < ST_STRIDE; ++k) st.h(c, k) = 0.0;
+    st.h(c, ST_ACTIVE) = 1.0;
+  }
+  int e = st.push();
+  if (e) return e;
+  std::vector<double> bb, tol(tol_in), rr;
+  if ((e = col_norms(bl, b, bb))) return e;
+  auto true_res = [&]() -> int {
+    int rs = M_hi(q, x);
+    if (rs) return rs;
+    if ((rs = bl.op(OP_XMY_NORM, &b, &q))) return rs;
+    std::swap(r, q);
+    return 0;
+  };
+  auto converged = [&]() -> bool {
+    for (int c = 0; c < n; ++c)
+      if (bb[c] > 0 && rr[c] > tol[c] * tol[c] * bb[c]) return false;
+    return true;
+  };
+  // a per-column coefficient in the state (ST_AUX) from the partials of a reduction
+  auto to_aux = [&]() -> int {
+    return launch_scalar(SC_DOT_TO_AUX, bl.partial, bl.gridx, n, st.d(), s) ? fail(LQ_EDEVICE, "scalar") : 0;
+  };
+  if ((e = true_res()) || (e = col_norms(bl, r, rr))) return e;
+  std::vector<double> inner_tolv(n, inner_tol);
+  int it = 0, k = 0;
+  while (it < maxiter && !converged()) {
+    if (k == kmax) {  // restart from the true residual
+      ++cnt.reliable;
+      if ((e = true_res()) || (e = col_norms(bl, r, rr))) return e;
+      k = 0;
+      if (converged()) break;
+    }
+    // z_k = P(r): a short sloppy BiCGStab from zero
+    Vec& zk = Z[k];
+    Vec& wk = W[k];
+    if ((e = vec_zero(zk))) return e;
+    Counters inner;
+    const int ri = bicgstab_mixed(bl, g, M_hi, M_lo, plo, zk, r, inner_tolv, inner_iters, delta, inner, M_fused);
+    if (ri != LQ_OK && ri != LQ_ENOCONV) return ri;
+    cnt.iters += inner.iters;
+    // w_k = M z_k, orthogonal to the earlier w_j (same combination on z_k)
+    if ((e = M_hi(wk, zk))) return e;
+    for (int j = 0; j < k; ++j) {
+      if ((e = bl.op(OP_DOT, &W[j], &wk)) || (e = to_aux())) return e;
+      if ((e = bl.op(OP_AXMY, &W[j], &wk, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)) ||
+          (e = bl.op(OP_AXMY, &Z[j], &zk, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)))
+        return e;
+    }
+    std::vector<double> ww;
+    if ((e = col_norms(bl, wk, ww))) return e;
+    if ((e = st.pull())) return e;
+    for (int c = 0; c < n; ++c) {
+      const double inv = ww[c] > 0 ? 1.0 / std::sqrt(ww[c]) : 0.0;
+      if (!std::isfinite(inv)) return fail(LQ_ENUMERIC, "GCR: non-finite direction norm");
+      st.h(c, ST_AUX) = inv;
+      st.h(c, ST_AUX + 1) = 0.0;
+    }
+    if ((e = st.push())) return e;
+    if ((e = bl.op(OP_SCALE, &wk, nullptr, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)) ||
+        (e = bl.op(OP_SCALE, &zk, nullptr, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)))
+      return e;
+    // alpha = <w_k, r>: x += alpha z_k, r -= alpha w_k
+    if ((e = bl.op(OP_DOT, &wk, &r)) || (e = to_aux())) return e;
+    if ((e = bl.op(OP_AXPY, &zk, &x, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)) ||
+        (e = bl.op(OP_AXMY, &wk, &r, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)))
+      return e;
+    if ((e = col_norms(bl, r, rr))) return e;
+    ++it;
+    ++k;
+    if (verbose()) {
+      double wr = 0.0;
+      for (int c = 0; c < n; ++c) wr = std::max(wr, bb[c] > 0 ? std::sqrt(rr[c] / bb[c]) : 0.0);
+      fprintf(stderr, "[lq] gcr step %d (%d inner iterations so far): worst rel. residual %.3e\n", it, cnt.iters,
+              wr);
+    }
+  }
+  // final true residual
+  if ((e = true_res()) || (e = col_norms(bl, r, rr))) return e;
+  return converged() ? LQ_OK : LQ_ENOCONV;
 }
 
 }  // namespace
@@ -711,12 +846,12 @@ static int overlap_solve(OpEnv& env, const lq_params* prm, int n_rhs, const doub
         if ((e = blr.op(OP_DOT, &p0, &ap))) return e;
         if (launch_ms_scalar_alpha(M, dsig.as<double>(), s)) return fail(LQ_EDEVICE, "ms alpha");
         {
-          Prof pr(c, "blas", s);
+          MsProf pr(c, M, false, s);
           if (launch_ms_xr(M, s)) return fail(LQ_EDEVICE, "ms xr");
         }
         if (launch_ms_scalar_beta(M, s)) return fail(LQ_EDEVICE, "ms beta");
         {
-          Prof pr(c, "blas", s);
+          MsProf pr(c, M, true, s);
           if (launch_ms_p(M, s)) return fail(LQ_EDEVICE, "ms p");
         }
         hipMemcpyAsync(hsh.data(), sh.p, sizeof(double) * 8 * ncs, hipMemcpyDeviceToHost, s);
@@ -881,8 +1016,11 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
       const bool fuse = getenv("LQ_NO_FUSED_REDUCTIONS") == nullptr;
       std::vector<double> tol_s(n_rhs, 0.5 * tol);
       for (int pass = 0; pass < 6; ++pass) {
-        const int rs = bicgstab_mixed(ble, g, M64, Mlo, plo, xe, bh, tol_s, maxiter, delta, cnt,
-                                      fuse ? &Mfused : nullptr);
+        const int rs = prm->solver == 2
+                           ? gcr_mixed(ble, g, M64, Mlo, plo, xe, bh, tol_s, maxiter, delta, cnt,
+                                       fuse ? &Mfused : nullptr, 8, 0.1, 50)
+                           : bicgstab_mixed(ble, g, M64, Mlo, plo, xe, bh, tol_s, maxiter, delta, cnt,
+                                            fuse ? &Mfused : nullptr);
         if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
         if ((e = tm_schur_reconstruct(env, x, xe, b))) return e;
         if ((e = rel_residual(bl, D64, x, b, res, g))) return e;
@@ -1014,18 +1152,24 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
       if (launch_ms_init(M, s)) return fail(LQ_EDEVICE, "ms init");
       std::vector<double> hsh((size_t)8 * ncol);
       Vec p0 = view(p, 0, n_rhs);
+      // <p_0, A p_0> from the stencil epilogue: partials over 64-site tiles
+      const int mtiles = (g.Vh + 63) / 64;
+      DBuf mred(sizeof(double) * 4 * (size_t)mtiles * n_rhs, s);
+      if (!mred.p) return fail(LQ_ENOMEM, "multi-shift partials");
+      MsArgs Ma = M;
+      Ma.partial = mred.as<double>();
+      Ma.gridx = mtiles;
       int it = 0;
       for (; it < maxiter; ++it) {
-        if ((e = stag_normal_even(env, pms, ap, p0, to, nullptr, m0 * m0))) return e;
-        if ((e = blr.op(OP_DOT, &p0, &ap))) return e;
-        if (launch_ms_scalar_alpha(M, dsig.as<double>(), s)) return fail(LQ_EDEVICE, "ms alpha");
+        if ((e = stag_normal_even(env, pms, ap, p0, to, nullptr, m0 * m0, mred.as<double>()))) return e;
+        if (launch_ms_scalar_alpha(Ma, dsig.as<double>(), s)) return fail(LQ_EDEVICE, "ms alpha");
         {
-          Prof pr(c, "blas", s);
+          MsProf pr(c, M, false, s);
           if (launch_ms_xr(M, s)) return fail(LQ_EDEVICE, "ms xr");
         }
         if (launch_ms_scalar_beta(M, s)) return fail(LQ_EDEVICE, "ms beta");
         {
-          Prof pr(c, "blas", s);
+          MsProf pr(c, M, true, s);
           if (launch_ms_p(M, s)) return fail(LQ_EDEVICE, "ms p");
         }
         if ((it & 3) == 3 || it < 4) {
@@ -1053,6 +1197,10 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
       Vec t = view(tolo, 0, i.ncol);
       return stag_normal_even(env, plo, o, i, t, dm2.as<double>(), 0.0);
     };
+    FusedFn Afused = [&](Vec& o, const Vec& i, int, double* red) {
+      Vec t = view(tolo, 0, i.ncol);
+      return stag_normal_even(env, plo, o, i, t, dm2.as<double>(), 0.0, red);
+    };
     // target half the tolerance, so the result keeps a margin below it; a
     // column still above the tolerance (rounding in the last update) goes
     // round again from its iterate with a tighter target
@@ -1060,7 +1208,7 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
     ColParam cpm{m2col, dm2.as<double>(), s};  // m^2 per column follows the solver's reordering
     std::vector<double> res;
     for (int pass = 0; pass < 4; ++pass) {
-      const int rs = cg_mixed(ble, g, A64, Alo, plo, y, brep, tolv, maxiter, delta, cnt, &cpm);
+      const int rs = cg_mixed(ble, g, A64, Alo, plo, y, brep, tolv, maxiter, delta, cnt, &cpm, &Afused);
       if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
       status = rs;
       if ((e = rel_residual(ble, A64, y, brep, res, g))) return e;

@@ -10,10 +10,14 @@
 // and the backward hop.  Epilogues:
 //   SEPI_HOP   out = k hop
 //   SEPI_XPAY  out = a_col x + k hop      (D = m + hop; M_e = m^2 - D_eo D_oe)
+//   SEPI_XPAY_DOT  the same and <x, out> per column and 64-site tile (CG's
+//              <p, M_e p> without a separate pass over p and M_e p)
 // FP16 links are stored divided by one FP32 scale per field (fat, long).
 // One thread owns one site and NR consecutive columns: the 16 links of a site
 // are loaded once for all NR columns (bitwise-identical per-column results
 // for every NR), and the NR neighbour loads of a hop are issued together.
+#include <type_traits>
+
 #include "lq_common.h"
 #include "lq_kernels.h"
 
@@ -85,10 +89,14 @@ __device__ __forceinline__ void stag_fwd(const StagArgs& A, const int c[4], int 
 template <int P, int EPI, int NR>
 __global__ void __launch_bounds__(kStencilMaxThreads) stag_kernel(StagArgs A) {
   using R = typename RealOf<P>::T;
+  constexpr bool RED = EPI == SEPI_XPAY_DOT;
   if (A.ncol <= 0) return;
   const int ngrp = (A.ncol + NR - 1) / NR;
-  int par, cb, grp, c[4];
-  if (stencil_site(A.g, A.par_out, A.slab, ngrp, A.sh, par, cb, grp, c) != 1) return;
+  int par, cb, grp, c[4], tile = 0;
+  const int status = stencil_site(A.g, A.par_out, A.slab, ngrp, A.sh, par, cb, grp, c, &tile);
+  // lanes past the end of the last tile stay only to join the wave reductions
+  if (status == 0 || (!RED && status != 1)) return;
+  const bool live = status == 1;
   const int col0 = grp * NR;
   const int nv = min(NR, A.ncol - col0);
   cx<R> af[NR][3], al[NR][3];
@@ -108,6 +116,9 @@ __global__ void __launch_bounds__(kStencilMaxThreads) stag_kernel(StagArgs A) {
   stag_fwd<P, 2, NR>(A, c, par, cb, col0, nv, af, al);
   stag_fwd<P, 3, NR>(A, c, par, cb, col0, nv, af, al);
   const R kf = (R)(A.k_hop * A.sfat), kl = (R)(A.k_hop * A.slong);
+  double red[NR][2];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[r][0] = red[r][1] = 0.0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     if (r >= nv) continue;
@@ -115,14 +126,42 @@ __global__ void __launch_bounds__(kStencilMaxThreads) stag_kernel(StagArgs A) {
     cx<R> out[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) out[a] = kf * af[r][a] + kl * al[r][a];
-    if constexpr (EPI == SEPI_XPAY) {
+    if constexpr (EPI == SEPI_XPAY || EPI == SEPI_XPAY_DOT) {
       cx<R> x[3];
       IO<P, 3>::template load<true>(A.x, blk_index(A.x, col, par), cb, x);
       const R a = A.acol ? (R)A.acol[col] : (R)A.a;
 #pragma unroll
       for (int i = 0; i < 3; ++i) out[i] = a * x[i] + out[i];
+      if constexpr (RED) {
+        if (live) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            red[r][0] += (double)x[i].re * (double)out[i].re + (double)x[i].im * (double)out[i].im;
+            red[r][1] += (double)x[i].re * (double)out[i].im - (double)x[i].im * (double)out[i].re;
+          }
+        }
+      }
     }
-    IO<P, 3>::template store<true>(A.out, blk_index(A.out, col, par), cb, out);
+    if (live) IO<P, 3>::template store<true>(A.out, blk_index(A.out, col, par), cb, out);
+  }
+  if constexpr (RED) {
+    // wave butterfly (fixed order) and one partial per (column, 64-site tile)
+    const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
+    const int ntile = (nsite + 63) >> 6;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r >= nv) continue;
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        for (int o = 32; o > 0; o >>= 1) red[r][k] += __shfl_xor(red[r][k], o);
+      if ((threadIdx.x & 63) == 0) {
+        double* q = A.red + ((int64_t)(col0 + r) * ntile + tile) * 4;
+        q[0] = red[r][0];
+        q[1] = red[r][1];
+        q[2] = 0.0;
+        q[3] = 0.0;
+      }
+    }
   }
 }
 
@@ -154,9 +193,15 @@ int launch_stag(const StagArgs& A, hipStream_t s) {
   if (!traversal_valid(A.g, A.slab)) return -1;
   const int bs = 0;
   int r;
-  if (A.prec == 64) r = A.epi == SEPI_HOP ? stag_nr<64, SEPI_HOP>(A, nr, bs, s) : stag_nr<64, SEPI_XPAY>(A, nr, bs, s);
-  else if (A.prec == 32) r = A.epi == SEPI_HOP ? stag_nr<32, SEPI_HOP>(A, nr, bs, s) : stag_nr<32, SEPI_XPAY>(A, nr, bs, s);
-  else r = A.epi == SEPI_HOP ? stag_nr<16, SEPI_HOP>(A, nr, bs, s) : stag_nr<16, SEPI_XPAY>(A, nr, bs, s);
+  auto pick = [&](auto p) -> int {
+    constexpr int P = decltype(p)::value;
+    if (A.epi == SEPI_HOP) return stag_nr<P, SEPI_HOP>(A, nr, bs, s);
+    if (A.epi == SEPI_XPAY) return stag_nr<P, SEPI_XPAY>(A, nr, bs, s);
+    return stag_nr<P, SEPI_XPAY_DOT>(A, nr, bs, s);
+  };
+  if (A.prec == 64) r = pick(std::integral_constant<int, 64>{});
+  else if (A.prec == 32) r = pick(std::integral_constant<int, 32>{});
+  else r = pick(std::integral_constant<int, 16>{});
   if (r) return r;
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }

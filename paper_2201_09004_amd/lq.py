@@ -29,6 +29,7 @@ EXPORTS = [
     "lq_init", "lq_finalize", "lq_last_error", "lq_version", "lq_gauge_load", "lq_gauge_load_dev",
     "lq_hisq_load", "lq_hisq_load_dev", "lq_field_free", "lq_apply", "lq_apply_dev", "lq_apply_noalloc", "lq_solve",
     "lq_solve_dev", "lq_eigs", "lq_hw_bounds", "lq_cheb_coeffs", "lq_copy_bandwidth", "lq_profile", "lq_profile_get",
+    "lq_profile_bytes",
     "lq_server_create", "lq_server_destroy", "lq_submit", "lq_poll", "lq_wait", "lq_server_stats",
 ]
 
@@ -107,6 +108,7 @@ def load():
         "lq_copy_bandwidth": ([P, C.c_size_t, C.c_int, D], C.c_int),
         "lq_profile": ([P, C.c_int], C.c_int),
         "lq_profile_get": ([P, C.c_char_p, C.POINTER(C.c_int64), D], C.c_int),
+        "lq_profile_bytes": ([P, C.c_char_p, D], C.c_int),
         "lq_server_create": ([P, C.c_size_t, C.c_int, C.POINTER(P)], C.c_int),
         "lq_server_destroy": ([P], C.c_int),
         "lq_submit": ([P, C.POINTER(lq_action), P, C.POINTER(lq_params), C.c_int, P, P, C.POINTER(lq_stats),
@@ -316,6 +318,12 @@ def lq_profile_get(ctx, name):
     n, ms = C.c_int64(), C.c_double()
     _check(load().lq_profile_get(ctx, name.encode(), C.byref(n), C.byref(ms)))
     return n.value, ms.value
+
+
+def lq_profile_bytes(ctx, name):
+    b = C.c_double()
+    _check(load().lq_profile_bytes(ctx, name.encode(), C.byref(b)))
+    return b.value
 
 
 def lq_server_create(ctx, hbm_budget, max_cols):

@@ -267,6 +267,28 @@ def test_tm_clover_eo_bicgstab(ctx, sloppy, fused, monkeypatch):
         L.lq_field_free(f)
 
 
+@pytest.mark.parametrize("sloppy", [32, 64])
+def test_tm_clover_eo_gcr(ctx, sloppy):
+    """Flexible GCR on the even-odd system (solver 2; sec. 2.1, Table 2's GCR),
+    directions from short sloppy BiCGStab solves: the FP64 true residual with
+    the oracle operator meets 1e-10 and the solution equals BiCGStab's."""
+    Lx = (4, 4, 6, 8)
+    U, f = _wilson_setup(ctx, Lx, 93, eps=0.2)
+    m, csw, mu = -0.0695, 1.0509, 0.01
+    b = synth.point_sources(Lx)[[0, 5, 10]]
+    try:
+        act = L.action(L.LQ_TM_CLOVER, m=m, mu=mu, c_sw=csw)
+        x, st = L.lq_solve(ctx, act, f, L.params(tol=1e-10, sloppy_bits=sloppy, solver=2), b)
+        print("gcr", st)
+        assert st["status"] == 0, st
+        F = W.field_strength(U)
+        assert _resid(lambda v: W.tm_clover(U, v, m, csw, mu, F=F), x, b) < 1e-10
+        x2, st2 = L.lq_solve(ctx, act, f, L.params(tol=1e-10, sloppy_bits=sloppy), b)
+        assert rel(x, x2) < 1e-8
+    finally:
+        L.lq_field_free(f)
+
+
 @pytest.mark.parametrize("sloppy", [32, 16])
 def test_hisq_multishift(ctx, sloppy):
     Lx = (4, 4, 4, 8)
