@@ -417,6 +417,76 @@ def bench_tm(args, L, torch):
     }
 
 
+def bench_tm_mg(args, L, torch):
+    """The twisted-clover propagator of the bench line (24^3x64, 12 point
+    sources, 1e-10) solved by GCR with the two-level multigrid preconditioner
+    (sec. 2.1, Table 2): the setup is timed once, then the solves."""
+    import synth
+
+    dev = torch.device("cuda:0")
+    n_rhs = 12
+    log("generating synthetic gauge field", TM_LAT)
+    U = synth.su3_field(TM_LAT, EPS, SEED)
+    U_d = torch.from_numpy(U).to(dev)
+    b_d = torch.from_numpy(synth.point_sources(TM_LAT)).to(dev)
+    x_d = torch.zeros_like(b_d)
+    del U
+    ctx = L.lq_init(0)
+    field = L.lq_gauge_load(ctx, TM_LAT, U_d)
+    del U_d
+    act = L.action(L.LQ_TM_CLOVER, m=M, mu=MU, c_sw=CSW)
+    block = tuple(int(v) for v in args.mg_block.split(","))
+    mp = L.mg_params(block=block, n_vec=args.mg_nvec, coarse_tol=args.mg_coarse_tol, nu_post=args.mg_nu,
+                     setup_passes=args.mg_passes, seed=11)
+    log("multigrid setup", block, args.mg_nvec)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    setup = L.lq_mg_setup(ctx, act, field, mp)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - ts
+    log("setup", round(t_setup, 3), "s", setup)
+    prm = L.params(tol=1e-10, solver=3, maxiter=300)
+    for _ in range(args.warmup):
+        x_d.zero_()
+        _, st = L.lq_solve(ctx, act, field, prm, b_d, x_d)
+        log("warmup stats", st)
+    torch.cuda.synchronize()
+    L.lq_profile(ctx, True)
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x_d.zero_()
+        _, st = L.lq_solve(ctx, act, field, prm, b_d, x_d)
+        stats.append(st)
+        log("step", st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) / args.steps * 1e3
+    value = n_rhs * args.steps / (t1 - t0)
+    worst = max(s["true_rel_res"] for s in stats)
+    names = [f"wilson{p}_site" for p in (32, 64)] + ["mg_restrict", "mg_prolong", "mg_coarse32", "mg_coarse64"]
+    vec_names = [f"blas{p}_{o}" for p in (32, 64) for o in BLAS_OPS]
+    kernels = profile_table(L, ctx, names + vec_names + ["blas"])
+    L.lq_profile(ctx, False)
+    roof = family_roofline(kernels, names + vec_names)
+    roof["share_of_step"] = round(kernels[roof["kernel"]]["total_ms"] / (ms_step * args.steps), 4)
+    L.lq_field_free(field)
+    L.lq_finalize(ctx)
+    return {
+        "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tm_clover_mg_gcr_24x24x24x64_12rhs", "lattice": list(TM_LAT), "n_rhs": n_rhs,
+                   "m": M, "c_sw": CSW, "mu": MU, "sources": "point", "tol": 1e-10, "block": list(block),
+                   "n_vec": args.mg_nvec, "coarse_tol": args.mg_coarse_tol, "nu_post": args.mg_nu,
+                   "setup_passes": args.mg_passes},
+        "setup_seconds": round(t_setup, 3), "setup_iters": setup["iters"],
+        "roofline": roof, "cpu_baseline": None, "worst_true_rel_res": worst,
+        "outer_iters": [s["iters"] for s in stats], "restarts": [s["reliable_updates"] for s in stats],
+        "kernels": kernels,
+    }
+
+
 def bench_hisq(args, L, torch):
     import numpy as np
 
@@ -951,7 +1021,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("tm", "hisq", "overlap", "overlap_mm", "overlap_sign", "overlap_lowmodes",
+    ap.add_argument("--workload", choices=("tm", "tm_mg", "hisq", "overlap", "overlap_mm", "overlap_sign", "overlap_lowmodes",
                                            "overlap_deflated", "serve", "wilson"), default="tm")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 single-column comparison")
@@ -960,6 +1030,11 @@ def main():
     ap.add_argument("--serve-rates", default="0.5,0.8,0.95", help="arrival rates as fractions of capacity (serve)")
     ap.add_argument("--serve-capacity", type=float, default=0.0,
                     help="closed-loop capacity in requests/s from an earlier run (serve; 0: measure it)")
+    ap.add_argument("--mg-block", default="4,4,4,4", help="multigrid aggregate extents x,y,z,t (tm_mg)")
+    ap.add_argument("--mg-nvec", type=int, default=24, help="multigrid near-null vectors (tm_mg)")
+    ap.add_argument("--mg-coarse-tol", type=float, default=0.1, help="coarse solve tolerance (tm_mg)")
+    ap.add_argument("--mg-nu", type=int, default=4, help="post-smoothing steps (tm_mg)")
+    ap.add_argument("--mg-passes", type=int, default=2, help="setup inverse-iteration passes (tm_mg)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -971,7 +1046,7 @@ def main():
     from paper_2201_09004_amd import lq as L
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    fn = {"tm": bench_tm, "hisq": bench_hisq, "overlap": bench_overlap, "overlap_mm": bench_overlap_mm,
+    fn = {"tm": bench_tm, "tm_mg": bench_tm_mg, "hisq": bench_hisq, "overlap": bench_overlap, "overlap_mm": bench_overlap_mm,
           "overlap_sign": bench_overlap_sign, "overlap_lowmodes": bench_overlap_lowmodes,
           "overlap_deflated": bench_overlap_deflated, "serve": bench_serve, "wilson": bench_wilson}[args.workload]
     out = fn(args, L, torch)

@@ -126,7 +126,10 @@ typedef struct {
   int32_t solver;          /* 0: default for the action, 1: CG on normal equations D^dag D (full lattice,
                               twisted clover and overlap), 2: twisted clover even-odd flexible GCR(8)
                               in FP64, each direction from a sloppy BiCGStab to 0.1 of the residual
-                              (at most 50 iterations), restarted from the true residual */
+                              (at most 50 iterations), restarted from the true residual; 3: flexible
+                              GCR on the full lattice preconditioned by the two-level multigrid of
+                              lq_mg_setup (Wilson and twisted clover; LQ_EINVAL without a setup for
+                              the same action on this field) */
   int32_t deflate;         /* overlap (solver 0): use this many resident chiral-sector low modes per
                               chirality (lq_eigs with LQ_EIG_OVERLAP) for the initial guess of every
                               sector solve; 0: none */
@@ -249,6 +252,52 @@ lq_status lq_eigs(lq_ctx *ctx, const lq_action *act, const lq_field *g, int whic
 
 /* Coefficients c_0..c_N of the Chebyshev interpolant of y^(-1/2) on [a, b] (host, FP64). */
 lq_status lq_cheb_coeffs(double a, double b, int N, double *c);
+
+/* ---- Multigrid (sec. 2.1, Table 2: the multigrid inverter and its reusable
+ * subspace setup) ------------------------------------------------------------
+ * Two-level aggregation multigrid for LQ_WILSON and LQ_TM_CLOVER.  The lattice
+ * is cut into aggregates of block[0..3] sites (coarse lattice L / block, x
+ * fastest).  n_vec near-null vectors are split by chirality on every aggregate
+ * and orthonormalised there (Gram-Schmidt in vector order), which gives the
+ * prolongator P; restriction is P^dag and the coarse operator is the Galerkin
+ * product D_c = P^dag D P, a nearest-neighbour stencil of (2 n_vec)^2 blocks.
+ * The setup is kept with the field (one hierarchy per field, replaced by the
+ * next setup, freed with the field) and used by lq_solve with solver = 3:
+ * flexible GCR(gcr_kmax) in FP64 on D x = b, each direction from one V-cycle
+ * in FP32: restrict the residual, solve the coarse system by BiCGStab to
+ * coarse_tol (at most coarse_maxiter iterations), prolong, then nu_post
+ * minimal-residual steps on D.
+ * Coarse vectors (lq_mg_apply): host [n_rhs][Vc][2][n_vec] complex, index 0 of
+ * the chirality axis for gamma5 = +1 (spins 0, 1 of the chiral basis). */
+typedef struct {
+  int32_t block[4];        /* aggregate extents (x, y, z, t): each >= 2; L / block even and >= 2 */
+  int32_t n_vec;           /* near-null vectors: 6, 12, 18, 24 or 30 (0: 24) */
+  int32_t setup_passes;    /* inverse-iteration passes from random vectors (0: 2) */
+  int32_t setup_maxiter;   /* even-odd BiCGStab iterations per pass at most (0: 200) */
+  int32_t coarse_maxiter;  /* V-cycle: coarse BiCGStab iterations at most (0: 100) */
+  double setup_tol;        /* relative residual of every setup solve (0: 1e-4) */
+  double coarse_tol;       /* V-cycle: coarse relative residual (0: 0.1) */
+  uint64_t seed;           /* random start vectors (splitmix64 of seed and element index) */
+  const double *null_vecs; /* optional host [n_vec][V][4][3]: the near-null vectors themselves, no passes */
+  int32_t nu_post;         /* minimal-residual smoothing steps on the fine level (0: 4) */
+  int32_t gcr_kmax;        /* outer flexible GCR restart length (0: 16) */
+} lq_mg_params;
+
+/* Computes and stores the hierarchy.  stats: iters = setup BiCGStab iterations,
+ * seconds = setup time.  LQ_EINVAL: action other than Wilson / twisted clover,
+ * block or n_vec out of range; LQ_ENUMERIC: a vector vanishes on an aggregate. */
+lq_status lq_mg_setup(lq_ctx *ctx, const lq_action *act, const lq_field *g, const lq_mg_params *mp,
+                      lq_stats *stats);
+
+/* The transfer and coarse operators of the stored hierarchy on host arrays (FP64
+ * in and out; prec_bits 64 or 32 selects the basis and coarse-operator copy):
+ *   LQ_MG_RESTRICT  in fine [n][V][4][3] -> out coarse [n][Vc][2][n_vec]
+ *   LQ_MG_PROLONG   in coarse -> out fine
+ *   LQ_MG_COARSE    in coarse -> out D_c in
+ * LQ_EINVAL without a hierarchy for this action. */
+enum { LQ_MG_RESTRICT = 0, LQ_MG_PROLONG = 1, LQ_MG_COARSE = 2 };
+lq_status lq_mg_apply(lq_ctx *ctx, const lq_action *act, const lq_field *g, int op, int prec_bits, int n_rhs,
+                      const double *in, double *out);
 
 /* HBM calibration: a plain copy kernel (one 16-byte chunk per lane) moves
  * `bytes` between two device buffers the library allocates and frees;

@@ -200,6 +200,7 @@ lq_status lq_field_free(lq_field* f) {
     for (auto p : kv.second.Ainv) fr(p);
   }
   for (auto& kv : f->eig) fr(kv.second.vecs);
+  mg_release(f->mg);
   delete f;
   return LQ_OK;
 }
@@ -267,9 +268,9 @@ static int check_solve(lq_ctx* c, const lq_action* act, const lq_field* g, const
   if (prm->n_shift < 0 || prm->n_shift > 64) return fail(LQ_EINVAL, "n_shift out of range");
   if (prm->n_shift > 1 && act->kind != LQ_HISQ && act->kind != LQ_OVERLAP)
     return fail(LQ_EINVAL, "several masses are implemented for HISQ and overlap");
-  if (prm->solver < 0 || prm->solver > 2) return fail(LQ_EINVAL, "solver must be 0, 1 or 2");
-  if (prm->solver == 2 && act->kind != LQ_TM_CLOVER)
-    return fail(LQ_EINVAL, "solver 2 (flexible GCR) is implemented for the twisted-clover action");
+  if (prm->solver < 0 || prm->solver > 3) return fail(LQ_EINVAL, "solver must be 0, 1, 2 or 3");
+  if ((prm->solver == 2 || prm->solver == 3) && act->kind != LQ_TM_CLOVER)
+    return fail(LQ_EINVAL, "solvers 2 (GCR) and 3 (multigrid) are implemented for the twisted-clover action");
   if (prm->n_shift > 1 && act->kind == LQ_OVERLAP && prm->solver == 1)
     return fail(LQ_EINVAL, "overlap: several masses need the chirally projected solver (solver = 0)");
   return 0;
@@ -337,6 +338,25 @@ lq_status lq_hw_bounds(lq_ctx* c, const lq_action* act, const lq_field* g, int i
   int e = hw_bounds(c, act, const_cast<lq_field*>(g), iters, lmin, lmax, c->stream);
   if (!e && hipStreamSynchronize(c->stream) != hipSuccess) e = fail(LQ_EDEVICE, "sync");
   return (lq_status)e;
+}
+
+lq_status lq_mg_setup(lq_ctx* c, const lq_action* act, const lq_field* g, const lq_mg_params* mp, lq_stats* stats) {
+  if (!c) return (lq_status)fail(LQ_EINVAL, "ctx is NULL");
+  int e = check_action(act, g);
+  if (e) return (lq_status)e;
+  hipSetDevice(c->device);
+  return (lq_status)mg_setup(c, act, const_cast<lq_field*>(g), mp, stats, c->stream);
+}
+
+lq_status lq_mg_apply(lq_ctx* c, const lq_action* act, const lq_field* g, int op, int prec, int n_rhs, const double* in,
+                      double* out) {
+  if (!c) return (lq_status)fail(LQ_EINVAL, "ctx is NULL");
+  int e = check_action(act, g);
+  if (e) return (lq_status)e;
+  if (n_rhs < 0) return (lq_status)fail(LQ_EINVAL, "n_rhs must be >= 0");
+  if (n_rhs > 0 && (!in || !out)) return (lq_status)fail(LQ_EINVAL, "NULL array");
+  hipSetDevice(c->device);
+  return (lq_status)mg_apply_host(c, act, const_cast<lq_field*>(g), op, prec, n_rhs, in, out, c->stream);
 }
 
 lq_status lq_cheb_coeffs(double a, double b, int N, double* c) {

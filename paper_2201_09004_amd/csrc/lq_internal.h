@@ -83,6 +83,24 @@ struct EigSet {
   std::vector<double> vals, res;  // eigenvalues (H_W: ascending |lambda|; sector: ascending) and residuals
 };
 
+// Two-level aggregation multigrid hierarchy of a field for one Wilson-type
+// action: aggregate maps, the chirality-split orthonormal basis Q and the
+// Galerkin coarse operator Dc (FP64 and FP32 copies), and the V-cycle settings
+struct MgHier {
+  int kind = 0;
+  double m = 0, mu = 0, csw = 0;  // action the hierarchy was built for
+  int block[4] = {0, 0, 0, 0}, Lc[4] = {0, 0, 0, 0};
+  int Vc = 0, B = 0, nv = 0, K = 0;
+  int *fine = nullptr, *nbr = nullptr, *face = nullptr, *cpar = nullptr;
+  void *Q64 = nullptr, *Q32 = nullptr, *Dc64 = nullptr, *Dc32 = nullptr;
+  Geom gc{};  // shape of coarse vectors: Vh = K * Vc pseudo-sites, one "parity"
+  double coarse_tol = 0.1;
+  int coarse_maxiter = 100, nu_post = 4, gcr_kmax = 16;
+  double setup_seconds = 0;
+  int setup_iters = 0;
+  MgGeom geom() const { return MgGeom{Vc, B, nv, K, fine, nbr, face, cpar}; }
+};
+
 }  // namespace lq
 
 struct lq_field {
@@ -98,6 +116,7 @@ struct lq_field {
   std::map<std::tuple<double, double, double>, lq::Clover> clover;
   std::map<double, lq::HwSpectrum> hw_spec;  // per rho: Lanczos spectrum of H_W^2
   std::map<std::tuple<int, double, int>, lq::EigSet> eig;  // (which, rho, chirality): low modes
+  lq::MgHier* mg = nullptr;  // multigrid hierarchy (lq_mg_setup), one per field
   std::mutex mtx;
 };
 
@@ -252,5 +271,16 @@ int add_modes(lq_ctx* c, const Geom& g, hipStream_t s, const EigSet& es, int n, 
               Vec& v, void* coef);
 void eig_release(lq_ctx* c);
 
+// multigrid (mg.cpp; setup and solve in solvers.cpp)
+int mg_init_maps(MgHier& h, const Geom& g, const int block[4], int nv);
+int mg_build(OpEnv& e, MgHier& h, Vec& vecs);  // basis from vecs (FP64, nv columns), then Dc
+void mg_release(MgHier* h);
+int mg_restrict(OpEnv& e, const MgHier& h, const Vec& fine, Vec& coarse);
+int mg_prolong(OpEnv& e, const MgHier& h, const Vec& coarse, Vec& fine);
+int mg_coarse_op(OpEnv& e, const MgHier& h, Vec& out, const Vec& in);
+int mg_apply_host(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec, int n_rhs, const double* in,
+                  double* out, hipStream_t s);
+int mg_setup(lq_ctx* c, const lq_action* act, lq_field* f, const lq_mg_params* mp, lq_stats* st, hipStream_t s);
+bool mg_matches(const MgHier* h, const lq_action* act);
 
 }  // namespace lq

@@ -143,6 +143,31 @@ int launch_ms_scalar_alpha(const MsArgs& A, const double* sigma, hipStream_t s);
 int launch_ms_scalar_beta(const MsArgs& A, hipStream_t s);
 int launch_ms_init(const MsArgs& A, hipStream_t s);
 
+// ------------------------------------------------------------ multigrid
+// Two-level aggregation: Vc aggregates of B fine sites, nv near-null vectors
+// (2 nv <= 64 and a multiple of 12); coarse vectors are Wilson-shaped fields of
+// K = 2 nv / 12 pseudo-sites per aggregate (npar = 1, Vh = K Vc).  Basis
+// Q[Vc][B][2][nv][6], coarse operator Dc[Vc][9][2nv][2nv] (see mg.hip).
+struct MgGeom {
+  int Vc, B, nv, K;
+  const int* fine;  // [Vc * B]: fine site cb | parity << 30 of (aggregate, in-block index)
+  const int* nbr;   // [Vc][8]: aggregate at Y + mu (2 mu) and Y - mu (2 mu + 1)
+  const int* face;  // [Vc * B]: bit 2 mu: lowest layer in mu, bit 2 mu + 1: highest layer
+  const int* cpar;  // [Vc]: coarse coordinate parities, bit mu = Y_mu & 1
+};
+int launch_mg_restrict(const MgGeom& m, int pf, const void* Q, FieldRef fine, int pc, FieldRef coarse, int ncol,
+                       hipStream_t s);
+int launch_mg_prolong(const MgGeom& m, int pc, FieldRef coarse, int pf, const void* Q, FieldRef fine, int ncol,
+                      hipStream_t s);
+int launch_mg_coarse(const MgGeom& m, int p, const void* Dc, FieldRef in, FieldRef out, int ncol, hipStream_t s);
+int launch_mg_gather(const MgGeom& m, FieldRef fine, void* Q64, hipStream_t s);
+int launch_mg_orth(const MgGeom& m, void* Q64, int* bad, hipStream_t s);
+int launch_mg_probe_source(const MgGeom& m, FieldRef coarse, int ncol, int k0, int cls, hipStream_t s);
+int launch_mg_probe_restrict(const MgGeom& m, const void* Q64, FieldRef fine, int ncol, int k0, int cls, void* Dc64,
+                             hipStream_t s);
+int launch_mg_narrow(const void* src64, void* dst32, int64_t n_complex, hipStream_t s);
+int launch_mg_random(FieldRef fine, int ncol, uint64_t seed, hipStream_t s);
+
 // profiling-free utilities
 int launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 int launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);

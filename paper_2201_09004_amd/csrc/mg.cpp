@@ -1,0 +1,272 @@
+// Host side of the two-level aggregation multigrid (sec. 2.1, Table 2):
+// aggregate maps, the basis and the Galerkin coarse operator, the transfer and
+// coarse operators on solver vectors, and the host-array entry point.
+//
+// The coarse operator is assembled by probing the fine operator.  Aggregates
+// are coloured by the parities of their coarse coordinates (16 classes);
+// for a class c and a coarse component k the probe is the prolongation of the
+// unit vector e_k on every aggregate of class c.  D applied to it reaches only
+// those aggregates and their nearest neighbours, whose classes differ from c
+// in one bit, and the neighbour in -mu and the one in +mu land on opposite
+// faces of an aggregate at least two sites deep.  So one FP64 application of D
+// per (class, component) gives column k of the self term of every class-c
+// aggregate and of the two mu-links of every aggregate next to one: 16 x 2 nv
+// applications in all, batched by columns.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "lq_internal.h"
+#include "lq_kernels.h"
+
+namespace lq {
+
+namespace {
+
+int upload_ints(int** dst, const std::vector<int>& v, hipStream_t s) {
+  if (hipMalloc((void**)dst, v.size() * sizeof(int)) != hipSuccess) {
+    (void)hipGetLastError();
+    *dst = nullptr;
+    return fail(LQ_ENOMEM, "multigrid maps");
+  }
+  if (hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(LQ_EDEVICE, "multigrid maps");
+  return 0;
+}
+
+void* dev_alloc(size_t bytes) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+}  // namespace
+
+void mg_release(MgHier* h) {
+  if (!h) return;
+  for (void* p : {(void*)h->fine, (void*)h->nbr, (void*)h->face, (void*)h->cpar, h->Q64, h->Q32, h->Dc64, h->Dc32})
+    if (p) hipFree(p);
+  delete h;
+}
+
+bool mg_matches(const MgHier* h, const lq_action* act) {
+  return h && act && h->kind == act->kind && h->m == act->m && h->mu == (act->kind == LQ_TM_CLOVER ? act->mu : 0.0) &&
+         h->csw == (act->kind == LQ_TM_CLOVER ? act->c_sw : 0.0);
+}
+
+int mg_init_maps(MgHier& h, const Geom& g, const int block[4], int nv) {
+  h.nv = nv;
+  h.K = 2 * nv / 12;
+  h.B = 1;
+  h.Vc = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    h.block[mu] = block[mu];
+    h.Lc[mu] = g.L[mu] / block[mu];
+    h.B *= block[mu];
+    h.Vc *= h.Lc[mu];
+  }
+  std::vector<int> fine((size_t)h.Vc * h.B), face((size_t)h.Vc * h.B), nbr((size_t)h.Vc * 8), cpar(h.Vc);
+  const int* Lc = h.Lc;
+  for (int Y = 0; Y < h.Vc; ++Y) {
+    int yc[4];
+    int r = Y;
+    for (int mu = 0; mu < 4; ++mu) {
+      yc[mu] = r % Lc[mu];
+      r /= Lc[mu];
+    }
+    cpar[Y] = (yc[0] & 1) | (yc[1] & 1) << 1 | (yc[2] & 1) << 2 | (yc[3] & 1) << 3;
+    for (int mu = 0; mu < 4; ++mu)
+      for (int sgn = 0; sgn < 2; ++sgn) {
+        int zc[4] = {yc[0], yc[1], yc[2], yc[3]};
+        zc[mu] = (zc[mu] + (sgn == 0 ? 1 : Lc[mu] - 1)) % Lc[mu];
+        nbr[(size_t)Y * 8 + 2 * mu + sgn] = zc[0] + Lc[0] * (zc[1] + Lc[1] * (zc[2] + Lc[2] * zc[3]));
+      }
+    for (int b = 0; b < h.B; ++b) {
+      int bc[4], x[4];
+      int q = b;
+      for (int mu = 0; mu < 4; ++mu) {
+        bc[mu] = q % block[mu];
+        q /= block[mu];
+        x[mu] = yc[mu] * block[mu] + bc[mu];
+      }
+      const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
+      const int cb = (x[0] >> 1) + g.Lxh * (x[1] + g.L[1] * (x[2] + g.L[2] * x[3]));
+      fine[(size_t)Y * h.B + b] = cb | par << 30;
+      int fb = 0;
+      for (int mu = 0; mu < 4; ++mu) {
+        if (bc[mu] == 0) fb |= 1 << (2 * mu);
+        if (bc[mu] == block[mu] - 1) fb |= 1 << (2 * mu + 1);
+      }
+      face[(size_t)Y * h.B + b] = fb;
+    }
+  }
+  hipStream_t s = nullptr;
+  int e = upload_ints(&h.fine, fine, s);
+  if (!e) e = upload_ints(&h.face, face, s);
+  if (!e) e = upload_ints(&h.nbr, nbr, s);
+  if (!e) e = upload_ints(&h.cpar, cpar, s);
+  if (e) return e;
+  h.gc = g;
+  h.gc.Vh = h.K * h.Vc;
+  return 0;
+}
+
+int mg_build(OpEnv& e, MgHier& h, Vec& vecs) {
+  hipStream_t s = e.s;
+  const MgGeom m = h.geom();
+  const int n2 = 2 * h.nv;
+  const size_t nq = (size_t)h.Vc * h.B * 2 * h.nv * 6;  // complex entries of Q
+  const size_t nd = (size_t)h.Vc * 9 * n2 * n2;          // complex entries of Dc
+  h.Q64 = dev_alloc(nq * 16);
+  h.Q32 = dev_alloc(nq * 8);
+  h.Dc64 = dev_alloc(nd * 16);
+  h.Dc32 = dev_alloc(nd * 8);
+  if (!h.Q64 || !h.Q32 || !h.Dc64 || !h.Dc32) return fail(LQ_ENOMEM, "multigrid basis and coarse operator");
+  DBuf bad(sizeof(int), s);
+  if (!bad.p) return fail(LQ_ENOMEM, "multigrid");
+  if (launch_fill_zero(bad.p, sizeof(int), s) || launch_mg_gather(m, vecs.f, h.Q64, s) ||
+      launch_mg_orth(m, h.Q64, bad.as<int>(), s) || launch_mg_narrow(h.Q64, h.Q32, (int64_t)nq, s) ||
+      launch_fill_zero(h.Dc64, nd * 16, s))
+    return fail(LQ_EDEVICE, "multigrid basis");
+  int nbad = 0;
+  if (hipMemcpyAsync(&nbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(LQ_EDEVICE, "multigrid basis");
+  if (nbad) return fail(LQ_ENUMERIC, "multigrid: a near-null vector vanishes on an aggregate");
+  // probing, 12 coarse components at a time
+  const int nb = std::min(12, n2);
+  Vec pc = make_vec(h.gc, 64, 12, nb, 1, 0, s);
+  Vec pf = make_vec(e.f->g, 64, 12, nb, 2, 0, s);
+  Vec df = make_vec(e.f->g, 64, 12, nb, 2, 0, s);
+  if (!pc.ok() || !pf.ok() || !df.ok()) return fail(LQ_ENOMEM, "multigrid probes");
+  for (int cls = 0; cls < 16; ++cls)
+    for (int k0 = 0; k0 < n2; k0 += nb) {
+      const int w = std::min(nb, n2 - k0);
+      Vec pcw = view(pc, 0, w), pfw = view(pf, 0, w), dfw = view(df, 0, w);
+      if (launch_mg_probe_source(m, pcw.f, w, k0, cls, s) ||
+          launch_mg_prolong(m, 64, pcw.f, 64, h.Q64, pfw.f, w, s))
+        return fail(LQ_EDEVICE, "multigrid probe");
+      int r = wilson_D(e, 64, dfw, pfw, false);
+      if (r) return r;
+      if (launch_mg_probe_restrict(m, h.Q64, dfw.f, w, k0, cls, h.Dc64, s)) return fail(LQ_EDEVICE, "multigrid probe");
+    }
+  if (launch_mg_narrow(h.Dc64, h.Dc32, (int64_t)nd, s)) return fail(LQ_EDEVICE, "multigrid coarse operator");
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(LQ_EDEVICE, "multigrid setup");
+  return 0;
+}
+
+int mg_restrict(OpEnv& e, const MgHier& h, const Vec& fine, Vec& coarse) {
+  Prof p(e.ctx, "mg_restrict", e.s, (double)h.Vc * h.B * 12 * fine.ncol * (fine.prec == 64 ? 16 : 8) +
+                                        (double)h.Vc * h.B * 2 * h.nv * 6 * (fine.prec == 64 ? 16 : 8));
+  const void* Q = fine.prec == 64 ? h.Q64 : h.Q32;
+  return launch_mg_restrict(h.geom(), fine.prec, Q, fine.f, coarse.prec, coarse.f, fine.ncol, e.s)
+             ? fail(LQ_EDEVICE, "multigrid restriction")
+             : 0;
+}
+
+int mg_prolong(OpEnv& e, const MgHier& h, const Vec& coarse, Vec& fine) {
+  Prof p(e.ctx, "mg_prolong", e.s, (double)h.Vc * h.B * 12 * fine.ncol * (fine.prec == 64 ? 16 : 8) +
+                                       (double)h.Vc * h.B * 2 * h.nv * 6 * (fine.prec == 64 ? 16 : 8));
+  const void* Q = fine.prec == 64 ? h.Q64 : h.Q32;
+  return launch_mg_prolong(h.geom(), coarse.prec, coarse.f, fine.prec, Q, fine.f, coarse.ncol, e.s)
+             ? fail(LQ_EDEVICE, "multigrid prolongation")
+             : 0;
+}
+
+int mg_coarse_op(OpEnv& e, const MgHier& h, Vec& out, const Vec& in) {
+  const int n2 = 2 * h.nv;
+  const double bytes = (double)h.Vc * 9 * n2 * n2 * (in.prec == 64 ? 16 : 8) +
+                       2.0 * h.Vc * n2 * in.ncol * (in.prec == 64 ? 16 : 8);
+  Prof p(e.ctx, in.prec == 64 ? "mg_coarse64" : "mg_coarse32", e.s, bytes);
+  e.n_apply += 1;
+  e.bytes += bytes;
+  return launch_mg_coarse(h.geom(), in.prec, in.prec == 64 ? h.Dc64 : h.Dc32, in.f, out.f, in.ncol, e.s)
+             ? fail(LQ_EDEVICE, "multigrid coarse operator")
+             : 0;
+}
+
+// ------------------------------------------------------------------ host arrays
+namespace {
+
+// coarse Vec (FP64) <-> host [n][Vc][2][nv] complex
+int coarse_to_host(const MgHier& h, const Vec& v, double* out, hipStream_t s) {
+  std::vector<double> raw(v.bytes / 8);
+  if (hipMemcpyAsync(raw.data(), v.f.data, v.bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(LQ_EDEVICE, "copy");
+  const int n2 = 2 * h.nv;
+  for (int col = 0; col < v.ncol; ++col)
+    for (int Y = 0; Y < h.Vc; ++Y)
+      for (int d = 0; d < n2; ++d) {
+        const int64_t i = tix(col, d % 12, 12, Y * h.K + d / 12, h.gc.Vh);
+        double* o = out + 2 * (((int64_t)col * h.Vc + Y) * n2 + d);
+        o[0] = raw[2 * i];
+        o[1] = raw[2 * i + 1];
+      }
+  return 0;
+}
+
+int coarse_from_host(const MgHier& h, Vec& v, const double* in, hipStream_t s) {
+  std::vector<double> raw(v.bytes / 8, 0.0);
+  const int n2 = 2 * h.nv;
+  for (int col = 0; col < v.ncol; ++col)
+    for (int Y = 0; Y < h.Vc; ++Y)
+      for (int d = 0; d < n2; ++d) {
+        const int64_t i = tix(col, d % 12, 12, Y * h.K + d / 12, h.gc.Vh);
+        const double* x = in + 2 * (((int64_t)col * h.Vc + Y) * n2 + d);
+        raw[2 * i] = x[0];
+        raw[2 * i + 1] = x[1];
+      }
+  if (hipMemcpyAsync(v.f.data, raw.data(), v.bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(LQ_EDEVICE, "copy");
+  return 0;
+}
+
+}  // namespace
+
+int mg_apply_host(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec, int n, const double* in,
+                  double* out, hipStream_t s) {
+  MgHier* h = f->mg;
+  if (!mg_matches(h, act)) return fail(LQ_EINVAL, "no multigrid setup for this action on this field");
+  if (prec != 64 && prec != 32) return fail(LQ_EINVAL, "prec_bits must be 64 or 32");
+  if (op < LQ_MG_RESTRICT || op > LQ_MG_COARSE) return fail(LQ_EINVAL, "unknown multigrid operator");
+  if (n <= 0) return 0;
+  const Geom& g = f->g;
+  OpEnv env{c, f, *act, s};
+  const size_t fine_doubles = (size_t)n * 2 * g.Vh * 24;
+  const size_t coarse_doubles = (size_t)n * h->Vc * 2 * h->nv * 2;
+  Vec c64 = make_vec(h->gc, 64, 12, n, 1, 0, s);
+  Vec clo = make_vec(h->gc, prec, 12, n, 1, 0, s);
+  Vec f64 = make_vec(g, 64, 12, n, 2, 0, s);
+  Vec flo = make_vec(g, prec, 12, n, 2, 0, s);
+  DBuf aos(sizeof(double) * std::max(fine_doubles, coarse_doubles), s);
+  if (!c64.ok() || !clo.ok() || !f64.ok() || !flo.ok() || !aos.p) return fail(LQ_ENOMEM, "multigrid buffers");
+  int e = 0;
+  if (op == LQ_MG_RESTRICT) {
+    if (hipMemcpyAsync(aos.p, in, fine_doubles * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(LQ_EDEVICE, "copy");
+    if (launch_pack_field(g, aos.as<double>(), n, 12, f64.f, 64, 2, s)) return fail(LQ_EDEVICE, "pack");
+    if ((e = vec_copy(flo, f64)) || (e = mg_restrict(env, *h, flo, c64))) return e;
+    return coarse_to_host(*h, c64, out, s);
+  }
+  if ((e = coarse_from_host(*h, c64, in, s))) return e;
+  if (op == LQ_MG_PROLONG) {
+    if ((e = mg_prolong(env, *h, c64, flo)) || (e = vec_copy(f64, flo))) return e;
+    if (launch_unpack_field(g, f64.f, 64, n, 12, aos.as<double>(), 2, s)) return fail(LQ_EDEVICE, "unpack");
+    if (hipMemcpyAsync(out, aos.p, fine_doubles * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(LQ_EDEVICE, "copy");
+    return 0;
+  }
+  Vec olo = make_vec(h->gc, prec, 12, n, 1, 0, s);
+  if (!olo.ok()) return fail(LQ_ENOMEM, "multigrid buffers");
+  if ((e = vec_copy(clo, c64)) || (e = mg_coarse_op(env, *h, olo, clo)) || (e = vec_copy(c64, olo))) return e;
+  return coarse_to_host(*h, c64, out, s);
+}
+
+}  // namespace lq

@@ -1,0 +1,461 @@
+// Two-level aggregation multigrid for the Wilson-type operators (sec. 2.1,
+// Table 2's multigrid inverter): transfer operators between the fine lattice
+// and the coarse lattice of aggregates, the coarse (Galerkin) stencil, and the
+// setup kernels that build them.
+//
+// Coarse vectors hold n2 = 2 nv complex numbers per coarse site, index
+// d = s nv + j (s = 0: chirality +, spins 0 and 1; s = 1: chirality -).  They
+// are stored as a Wilson-shaped field with K = n2 / 12 pseudo-sites per coarse
+// site (npar = 1, Vh = K Vc), so the vector kernels of the solvers run on them
+// unchanged; component d of coarse site Y is component d % 12 of pseudo-site
+// Y K + d / 12.
+//
+// The basis Q[Vc][B][2][nv][6] holds, per aggregate, in-block site, chirality
+// and vector, the six spin-colour components of that chirality (orthonormal
+// over each (aggregate, chirality) after launch_mg_orth).  The coarse operator
+// Dc[Vc][9][n2 (column k)][n2 (row i)]: direction 0 is the aggregate itself,
+// 1 + 2 mu couples to Y + mu and 2 + 2 mu to Y - mu; rows are contiguous so
+// that the threads of a coarse site read a column in one pass.
+#include "lq_common.h"
+#include "lq_kernels.h"
+
+namespace lq {
+
+namespace {
+
+template <int P> struct CxT;
+template <> struct CxT<64> { using T = double2; using R = double; };
+template <> struct CxT<32> { using T = float2; using R = float; };
+
+// one complex number of a coarse vector
+template <int P> struct CIO;
+template <> struct CIO<64> {
+  static __device__ __forceinline__ cx<double> ld(const FieldRef& f, int col, int q, int c) {
+    const double2 v = ((const double2*)f.data)[tix(col, c, 12, q, f.Vh)];
+    return {v.x, v.y};
+  }
+  static __device__ __forceinline__ void st(const FieldRef& f, int col, int q, int c, cx<double> v) {
+    ((double2*)f.data)[tix(col, c, 12, q, f.Vh)] = make_double2(v.re, v.im);
+  }
+};
+template <> struct CIO<32> {
+  static __device__ __forceinline__ cx<float> ld(const FieldRef& f, int col, int q, int c) {
+    const float2 v = ((const float2*)f.data)[2 * tix(col, c >> 1, 6, q, f.Vh) + (c & 1)];
+    return {v.x, v.y};
+  }
+  static __device__ __forceinline__ void st(const FieldRef& f, int col, int q, int c, cx<float> v) {
+    ((float2*)f.data)[2 * tix(col, c >> 1, 6, q, f.Vh) + (c & 1)] = make_float2(v.re, v.im);
+  }
+};
+template <int P>
+__device__ __forceinline__ cx<typename CxT<P>::R> cld(const FieldRef& f, int col, int Y, int d, int K) {
+  return CIO<P>::ld(f, col, Y * K + d / 12, d % 12);
+}
+template <int P>
+__device__ __forceinline__ void cst(const FieldRef& f, int col, int Y, int d, int K, cx<typename CxT<P>::R> v) {
+  CIO<P>::st(f, col, Y * K + d / 12, d % 12, v);
+}
+
+// the six components of chirality s of a fine Wilson site (FP64 / FP32 layouts)
+template <int P> struct HalfIO;
+template <> struct HalfIO<64> {
+  static __device__ __forceinline__ void ld(const FieldRef& f, int64_t blk, int cb, int s, cx<double>* v) {
+    const double2* p = (const double2*)f.data;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double2 d = p[tix(blk, 6 * s + c, 12, cb, f.Vh)];
+      v[c] = {d.x, d.y};
+    }
+  }
+  static __device__ __forceinline__ void st(const FieldRef& f, int64_t blk, int cb, int s, const cx<double>* v) {
+    double2* p = (double2*)f.data;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) p[tix(blk, 6 * s + c, 12, cb, f.Vh)] = make_double2(v[c].re, v[c].im);
+  }
+};
+template <> struct HalfIO<32> {
+  static __device__ __forceinline__ void ld(const FieldRef& f, int64_t blk, int cb, int s, cx<float>* v) {
+    const float4* p = (const float4*)f.data;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float4 d = p[tix(blk, 3 * s + k, 6, cb, f.Vh)];
+      v[2 * k] = {d.x, d.y};
+      v[2 * k + 1] = {d.z, d.w};
+    }
+  }
+  static __device__ __forceinline__ void st(const FieldRef& f, int64_t blk, int cb, int s, const cx<float>* v) {
+    float4* p = (float4*)f.data;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      p[tix(blk, 3 * s + k, 6, cb, f.Vh)] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+  }
+};
+
+constexpr int MG_CB = 4;  // columns per thread in the transfer and coarse kernels
+
+__device__ __forceinline__ void fine_site(const MgGeom& m, int yb, int& cb, int& par) {
+  const int v = m.fine[yb];
+  cb = v & 0x3fffffff;
+  par = (v >> 30) & 1;
+}
+
+// ---------------------------------------------------------------- transfers
+// restriction: coarse(col, Y, s nv + j) = sum over the aggregate's sites of
+// q_{Y,s,j}^dag v_s; one thread per (Y, s, j), MG_CB columns per thread
+template <int PF, int PC>
+__global__ void __launch_bounds__(64) mg_restrict_kernel(MgGeom m, const void* Qv, FieldRef fine, FieldRef coarse,
+                                                          int ncol) {
+  using R = typename CxT<PF>::R;
+  const int Y = blockIdx.x, t = threadIdx.x, n2 = 2 * m.nv;
+  if (t >= n2) return;
+  const int s = t / m.nv, j = t - s * m.nv;
+  const int col0 = blockIdx.y * MG_CB;
+  const int nc = min(MG_CB, ncol - col0);
+  const cx<R>* Q = (const cx<R>*)Qv;
+  cx<R> acc[MG_CB];
+#pragma unroll
+  for (int c = 0; c < MG_CB; ++c) acc[c] = {0, 0};
+  for (int b = 0; b < m.B; ++b) {
+    const int yb = Y * m.B + b;
+    int cb, par;
+    fine_site(m, yb, cb, par);
+    const cx<R>* q = Q + (((int64_t)yb * 2 + s) * m.nv + j) * 6;
+    cx<R> qv[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) qv[c] = q[c];
+#pragma unroll
+    for (int cc = 0; cc < MG_CB; ++cc) {
+      if (cc < nc) {
+        cx<R> v[6];
+        HalfIO<PF>::ld(fine, (int64_t)(col0 + cc) * 2 + par, cb, s, v);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) fmac(acc[cc], qv[c], v[c]);
+      }
+    }
+  }
+  using RC = typename CxT<PC>::R;
+#pragma unroll
+  for (int cc = 0; cc < MG_CB; ++cc)
+    if (cc < nc) cst<PC>(coarse, col0 + cc, Y, t, m.K, cx<RC>{(RC)acc[cc].re, (RC)acc[cc].im});
+}
+
+// prolongation: fine(col, y)_s = sum_j coarse(col, Y(y), s nv + j) q_{Y,s,j}(y);
+// one thread per (aggregate site, chirality)
+template <int PC, int PF>
+__global__ void __launch_bounds__(256) mg_prolong_kernel(MgGeom m, FieldRef coarse, const void* Qv, FieldRef fine,
+                                                          int ncol) {
+  using R = typename CxT<PF>::R;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)m.Vc * m.B * 2) return;
+  const int yb = (int)(gid >> 1), s = (int)(gid & 1);
+  const int Y = yb / m.B;
+  const int col0 = blockIdx.y * MG_CB;
+  const int nc = min(MG_CB, ncol - col0);
+  const cx<R>* q = (const cx<R>*)Qv + (int64_t)yb * 2 * m.nv * 6 + (int64_t)s * m.nv * 6;
+  cx<R> acc[MG_CB][6];
+#pragma unroll
+  for (int cc = 0; cc < MG_CB; ++cc)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[cc][c] = {0, 0};
+  for (int j = 0; j < m.nv; ++j) {
+    cx<R> qv[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) qv[c] = q[j * 6 + c];
+#pragma unroll
+    for (int cc = 0; cc < MG_CB; ++cc) {
+      if (cc < nc) {
+        const auto a = cld<PC>(coarse, col0 + cc, Y, s * m.nv + j, m.K);
+        const cx<R> ar = {(R)a.re, (R)a.im};
+#pragma unroll
+        for (int c = 0; c < 6; ++c) fma(acc[cc][c], qv[c], ar);
+      }
+    }
+  }
+  int cb, par;
+  fine_site(m, yb, cb, par);
+#pragma unroll
+  for (int cc = 0; cc < MG_CB; ++cc)
+    if (cc < nc) HalfIO<PF>::st(fine, (int64_t)(col0 + cc) * 2 + par, cb, s, acc[cc]);
+}
+
+// ---------------------------------------------------------------- coarse stencil
+// out(col, Y, i) = sum_d sum_k Dc[Y][d][k][i] in(col, N_d(Y), k); one thread per row i
+template <int P>
+__global__ void __launch_bounds__(64) mg_coarse_kernel(MgGeom m, const void* Dcv, FieldRef in, FieldRef out,
+                                                        int ncol) {
+  using R = typename CxT<P>::R;
+  const int Y = blockIdx.x, i = threadIdx.x, n2 = 2 * m.nv;
+  if (i >= n2) return;
+  const int col0 = blockIdx.y * MG_CB;
+  const int nc = min(MG_CB, ncol - col0);
+  cx<R> acc[MG_CB];
+#pragma unroll
+  for (int c = 0; c < MG_CB; ++c) acc[c] = {0, 0};
+  for (int d = 0; d < 9; ++d) {
+    const int Yn = d == 0 ? Y : m.nbr[Y * 8 + d - 1];
+    const cx<R>* M = (const cx<R>*)Dcv + ((int64_t)Y * 9 + d) * n2 * n2 + i;
+    for (int k = 0; k < n2; ++k) {
+      const cx<R> a = M[(int64_t)k * n2];
+#pragma unroll
+      for (int cc = 0; cc < MG_CB; ++cc)
+        if (cc < nc) fma(acc[cc], a, cld<P>(in, col0 + cc, Yn, k, m.K));
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < MG_CB; ++cc)
+    if (cc < nc) cst<P>(out, col0 + cc, Y, i, m.K, acc[cc]);
+}
+
+// ---------------------------------------------------------------- setup
+// Q[:, :, s, j, :] = chirality-s half of fine column j (FP64)
+__global__ void __launch_bounds__(256) mg_gather_kernel(MgGeom m, FieldRef fine, double2* Q) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)m.Vc * m.B * 2 * m.nv;
+  if (gid >= n) return;
+  const int j = (int)(gid % m.nv);
+  const int s = (int)((gid / m.nv) & 1);
+  const int yb = (int)(gid / (2 * m.nv));
+  int cb, par;
+  fine_site(m, yb, cb, par);
+  cx<double> v[6];
+  HalfIO<64>::ld(fine, (int64_t)j * 2 + par, cb, s, v);
+  double2* q = Q + (((int64_t)yb * 2 + s) * m.nv + j) * 6;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) q[c] = make_double2(v[c].re, v[c].im);
+}
+
+__device__ __forceinline__ double2 block_sum2(double2 v, double2* sm) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o);
+    v.y += __shfl_xor(v.y, o);
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();  // sm is free again
+  if ((threadIdx.x & 63) == 0) sm[w] = v;
+  __syncthreads();
+  double2 r = make_double2(0.0, 0.0);
+  const int nw = blockDim.x >> 6;
+  for (int k = 0; k < nw; ++k) {
+    r.x += sm[k].x;
+    r.y += sm[k].y;
+  }
+  return r;
+}
+
+// Gram-Schmidt in vector order, two passes, on every (aggregate, chirality):
+// one workgroup of 256 threads each; vectors of B*6 complex numbers
+__global__ void __launch_bounds__(256) mg_orth_kernel(MgGeom m, double2* Q, int* bad) {
+  __shared__ double2 sm[4];
+  const int Y = blockIdx.x >> 1, s = blockIdx.x & 1;
+  const int n = m.B * 6;
+  const int64_t sstride = (int64_t)2 * m.nv * 6;  // between in-block sites
+  auto at = [&](int j, int e) -> double2& {
+    const int b = e / 6, c = e - 6 * (e / 6);
+    return Q[((int64_t)(Y * m.B + b)) * sstride + ((int64_t)s * m.nv + j) * 6 + c];
+  };
+  for (int j = 0; j < m.nv; ++j) {
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i < j; ++i) {
+        double2 d = make_double2(0.0, 0.0);
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+          const double2 a = at(i, e), b = at(j, e);
+          d.x += a.x * b.x + a.y * b.y;
+          d.y += a.x * b.y - a.y * b.x;
+        }
+        d = block_sum2(d, sm);
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+          const double2 a = at(i, e);
+          double2& b = at(j, e);
+          b.x -= d.x * a.x - d.y * a.y;
+          b.y -= d.x * a.y + d.y * a.x;
+        }
+        __syncthreads();
+      }
+    }
+    double2 nn = make_double2(0.0, 0.0);
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      const double2 a = at(j, e);
+      nn.x += a.x * a.x + a.y * a.y;
+    }
+    nn = block_sum2(nn, sm);
+    const double inv = nn.x > 0.0 ? 1.0 / sqrt(nn.x) : 0.0;
+    if (nn.x <= 0.0 && threadIdx.x == 0) atomicAdd(bad, 1);
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      double2& a = at(j, e);
+      a.x *= inv;
+      a.y *= inv;
+    }
+    __syncthreads();
+  }
+}
+
+// probe sources: column kk is the coarse unit vector of component k0 + kk on
+// every aggregate of coarse parity class cls
+__global__ void __launch_bounds__(256) mg_probe_source_kernel(MgGeom m, FieldRef coarse, int ncol, int k0, int cls) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n2 = 2 * m.nv;
+  if (gid >= (int64_t)ncol * m.Vc * n2) return;
+  const int d = (int)(gid % n2);
+  const int Y = (int)((gid / n2) % m.Vc);
+  const int col = (int)(gid / ((int64_t)n2 * m.Vc));
+  const double v = (d == k0 + col && m.cpar[Y] == cls) ? 1.0 : 0.0;
+  cst<64>(coarse, col, Y, d, m.K, cx<double>{v, 0.0});
+}
+
+// Columns k0.. of Dc from D applied to the probe sources of class cls: an
+// aggregate of class cls restricts its whole block into the self term; an
+// aggregate whose class differs in the bit of direction mu only receives the
+// hops of its two mu-neighbours, the one at Y - mu on its lower mu-face and
+// the one at Y + mu on its upper mu-face (blocks are at least 2 sites deep, so
+// the faces are disjoint).  Other aggregates receive nothing.
+__global__ void __launch_bounds__(64) mg_probe_restrict_kernel(MgGeom m, const double2* Q, FieldRef fine, int ncol,
+                                                                int k0, int cls, double2* Dc) {
+  const int Y = blockIdx.x, t = threadIdx.x, n2 = 2 * m.nv;
+  if (t >= n2) return;
+  const int s = t / m.nv, j = t - s * m.nv;
+  const int bits = m.cpar[Y] ^ cls;
+  int mu = -1;
+  if (bits != 0) {
+    if (bits & (bits - 1)) return;
+    mu = __ffs(bits) - 1;
+  }
+  for (int kk = 0; kk < ncol; ++kk) {
+    cx<double> lo = {0, 0}, hi = {0, 0};
+    for (int b = 0; b < m.B; ++b) {
+      const int yb = Y * m.B + b;
+      const int fb = m.face[yb];
+      const bool in_lo = mu < 0 || (fb >> (2 * mu)) & 1;
+      const bool in_hi = mu >= 0 && (fb >> (2 * mu + 1)) & 1;
+      if (!in_lo && !in_hi) continue;
+      int cb, par;
+      fine_site(m, yb, cb, par);
+      cx<double> v[6];
+      HalfIO<64>::ld(fine, (int64_t)kk * 2 + par, cb, s, v);
+      const double2* q = Q + (((int64_t)yb * 2 + s) * m.nv + j) * 6;
+      cx<double> acc = {0, 0};
+#pragma unroll
+      for (int c = 0; c < 6; ++c) fmac(acc, cx<double>{q[c].x, q[c].y}, v[c]);
+      if (in_lo) lo = lo + acc;
+      if (in_hi) hi = hi + acc;
+    }
+    const int k = k0 + kk;
+    if (mu < 0) {
+      Dc[(((int64_t)Y * 9) * n2 + k) * n2 + t] = make_double2(lo.re, lo.im);
+    } else {
+      Dc[(((int64_t)Y * 9 + 2 + 2 * mu) * n2 + k) * n2 + t] = make_double2(lo.re, lo.im);
+      Dc[(((int64_t)Y * 9 + 1 + 2 * mu) * n2 + k) * n2 + t] = make_double2(hi.re, hi.im);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) mg_narrow_kernel(const double2* src, float2* dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = src[i];
+    dst[i] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+// splitmix64 (Steele, Lea, Flood 2014) of (seed, element): uniform in [-1, 1)
+__device__ __forceinline__ double mix_uniform(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ void __launch_bounds__(256) mg_random_kernel(FieldRef fine, int ncol, uint64_t seed) {
+  const int64_t n = (int64_t)ncol * 2 * fine.Vh;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t blk = i / fine.Vh;
+    const int cb = (int)(i - blk * fine.Vh);
+    cx<double> v[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const uint64_t e = ((uint64_t)i * 12 + c) * 2;
+      v[c] = {mix_uniform(seed, e), mix_uniform(seed, e + 1)};
+    }
+    IO<64, 12>::store(fine, blk, cb, v);
+  }
+}
+
+inline int grid_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 1 << 20); }
+
+}  // namespace
+
+int launch_mg_restrict(const MgGeom& m, int pf, const void* Q, FieldRef fine, int pc, FieldRef coarse, int ncol,
+                       hipStream_t s) {
+  if (ncol <= 0) return 0;
+  if (2 * m.nv > 64) return -1;
+  dim3 grid(m.Vc, (ncol + MG_CB - 1) / MG_CB), block(64);
+  if (pf == 64 && pc == 64) mg_restrict_kernel<64, 64><<<grid, block, 0, s>>>(m, Q, fine, coarse, ncol);
+  else if (pf == 32 && pc == 64) mg_restrict_kernel<32, 64><<<grid, block, 0, s>>>(m, Q, fine, coarse, ncol);
+  else if (pf == 32 && pc == 32) mg_restrict_kernel<32, 32><<<grid, block, 0, s>>>(m, Q, fine, coarse, ncol);
+  else if (pf == 64 && pc == 32) mg_restrict_kernel<64, 32><<<grid, block, 0, s>>>(m, Q, fine, coarse, ncol);
+  else return -1;
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_mg_prolong(const MgGeom& m, int pc, FieldRef coarse, int pf, const void* Q, FieldRef fine, int ncol,
+                      hipStream_t s) {
+  if (ncol <= 0) return 0;
+  const int64_t n = (int64_t)m.Vc * m.B * 2;
+  dim3 grid((unsigned)((n + 255) / 256), (ncol + MG_CB - 1) / MG_CB), block(256);
+  if (pc == 64 && pf == 64) mg_prolong_kernel<64, 64><<<grid, block, 0, s>>>(m, coarse, Q, fine, ncol);
+  else if (pc == 64 && pf == 32) mg_prolong_kernel<64, 32><<<grid, block, 0, s>>>(m, coarse, Q, fine, ncol);
+  else if (pc == 32 && pf == 32) mg_prolong_kernel<32, 32><<<grid, block, 0, s>>>(m, coarse, Q, fine, ncol);
+  else if (pc == 32 && pf == 64) mg_prolong_kernel<32, 64><<<grid, block, 0, s>>>(m, coarse, Q, fine, ncol);
+  else return -1;
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_mg_coarse(const MgGeom& m, int p, const void* Dc, FieldRef in, FieldRef out, int ncol, hipStream_t s) {
+  if (ncol <= 0) return 0;
+  if (2 * m.nv > 64) return -1;
+  dim3 grid(m.Vc, (ncol + MG_CB - 1) / MG_CB), block(64);
+  if (p == 64) mg_coarse_kernel<64><<<grid, block, 0, s>>>(m, Dc, in, out, ncol);
+  else if (p == 32) mg_coarse_kernel<32><<<grid, block, 0, s>>>(m, Dc, in, out, ncol);
+  else return -1;
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_mg_gather(const MgGeom& m, FieldRef fine, void* Q64, hipStream_t s) {
+  const int64_t n = (int64_t)m.Vc * m.B * 2 * m.nv;
+  mg_gather_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(m, fine, (double2*)Q64);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_mg_orth(const MgGeom& m, void* Q64, int* bad, hipStream_t s) {
+  mg_orth_kernel<<<m.Vc * 2, 256, 0, s>>>(m, (double2*)Q64, bad);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_mg_probe_source(const MgGeom& m, FieldRef coarse, int ncol, int k0, int cls, hipStream_t s) {
+  const int64_t n = (int64_t)ncol * m.Vc * 2 * m.nv;
+  if (n <= 0) return 0;
+  mg_probe_source_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(m, coarse, ncol, k0, cls);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_mg_probe_restrict(const MgGeom& m, const void* Q64, FieldRef fine, int ncol, int k0, int cls, void* Dc64,
+                             hipStream_t s) {
+  if (ncol <= 0) return 0;
+  if (2 * m.nv > 64) return -1;
+  mg_probe_restrict_kernel<<<m.Vc, 64, 0, s>>>(m, (const double2*)Q64, fine, ncol, k0, cls, (double2*)Dc64);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_mg_narrow(const void* src64, void* dst32, int64_t n_complex, hipStream_t s) {
+  if (n_complex <= 0) return 0;
+  mg_narrow_kernel<<<grid_for(n_complex, 256), 256, 0, s>>>((const double2*)src64, (float2*)dst32, n_complex);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_mg_random(FieldRef fine, int ncol, uint64_t seed, hipStream_t s) {
+  const int64_t n = (int64_t)ncol * 2 * fine.Vh;
+  if (n <= 0) return 0;
+  mg_random_kernel<<<grid_for(n, 256), 256, 0, s>>>(fine, ncol, seed);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+}  // namespace lq

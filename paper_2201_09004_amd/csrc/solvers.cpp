@@ -492,16 +492,18 @@ int bicgstab_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, 
 }
 
 // Flexible GCR (generalised conjugate residual, restarted after kmax
-// directions) in FP64 on a non-Hermitian M, preconditioned by a short sloppy
-// BiCGStab solve of M z = r (to `inner_tol` relative to r, at most
-// `inner_iters` iterations): every outer direction z_k = P(r) may come from a
-// different preconditioner, so M z_k is orthogonalised against the earlier
-// M z_j (modified Gram-Schmidt, applied to z_k alike) and the residual is
-// minimised over the span.  The outer recurrence is FP64, so r stays the
-// true residual up to rounding; it is recomputed at every restart.
-int gcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int plo, Vec& x, Vec& b,
-              const std::vector<double>& tol_in, int maxiter, double delta, Counters& cnt, const FusedFn* M_fused,
-              int kmax, double inner_tol, int inner_iters) {
+// directions) in FP64 on a non-Hermitian M with a variable preconditioner:
+// every outer direction z_k = K(r) may come from a different preconditioner
+// (a short sloppy Krylov solve, a multigrid cycle), so M z_k is orthogonalised
+// against the earlier M z_j (modified Gram-Schmidt, applied to z_k alike) and
+// the residual is minimised over the span.  The outer recurrence is FP64, so r
+// stays the true residual up to rounding; it is recomputed at every restart.
+// K may add to cnt; the outer steps are returned in *steps.
+using PrecFn = std::function<int(Vec& z, Vec& r, Counters& cnt)>;
+
+int fgcr(Blas& bl, const Geom& g, const OpFn& M_hi, const PrecFn& K, Vec& x, Vec& b,
+         const std::vector<double>& tol_in, int maxiter, Counters& cnt, int kmax, const char* tag,
+         int* steps = nullptr) {
   const int n = b.ncol, nc = b.nc, npar = b.npar, par0 = b.par0;
   hipStream_t s = bl.s;
   Vec r = make_vec(g, 64, nc, n, npar, par0, s), q = make_vec(g, 64, nc, n, npar, par0, s);
@@ -538,7 +540,6 @@ int gcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int p
     return launch_scalar(SC_DOT_TO_AUX, bl.partial, bl.gridx, n, st.d(), s) ? fail(LQ_EDEVICE, "scalar") : 0;
   };
   if ((e = true_res()) || (e = col_norms(bl, r, rr))) return e;
-  std::vector<double> inner_tolv(n, inner_tol);
   int it = 0, k = 0;
   while (it < maxiter && !converged()) {
     if (k == kmax) {  // restart from the true residual
@@ -547,14 +548,10 @@ int gcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int p
       k = 0;
       if (converged()) break;
     }
-    // z_k = P(r): a short sloppy BiCGStab from zero
+    // z_k = K(r)
     Vec& zk = Z[k];
     Vec& wk = W[k];
-    if ((e = vec_zero(zk))) return e;
-    Counters inner;
-    const int ri = bicgstab_mixed(bl, g, M_hi, M_lo, plo, zk, r, inner_tolv, inner_iters, delta, inner, M_fused);
-    if (ri != LQ_OK && ri != LQ_ENOCONV) return ri;
-    cnt.iters += inner.iters;
+    if ((e = K(zk, r, cnt))) return e;
     // w_k = M z_k, orthogonal to the earlier w_j (same combination on z_k)
     if ((e = M_hi(wk, zk))) return e;
     for (int j = 0; j < k; ++j) {
@@ -587,13 +584,133 @@ int gcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int p
     if (verbose()) {
       double wr = 0.0;
       for (int c = 0; c < n; ++c) wr = std::max(wr, bb[c] > 0 ? std::sqrt(rr[c] / bb[c]) : 0.0);
-      fprintf(stderr, "[lq] gcr step %d (%d inner iterations so far): worst rel. residual %.3e\n", it, cnt.iters,
-              wr);
+      fprintf(stderr, "[lq] %s step %d (%d iterations so far): worst rel. residual %.3e\n", tag, it, cnt.iters, wr);
     }
   }
+  if (steps) *steps = it;
   // final true residual
   if ((e = true_res()) || (e = col_norms(bl, r, rr))) return e;
   return converged() ? LQ_OK : LQ_ENOCONV;
+}
+
+// GCR preconditioned by a short sloppy BiCGStab solve of M z = r from zero
+// (to inner_tol relative to r, at most inner_iters iterations); cnt.iters
+// counts the inner iterations
+int gcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int plo, Vec& x, Vec& b,
+              const std::vector<double>& tol_in, int maxiter, double delta, Counters& cnt, const FusedFn* M_fused,
+              int kmax, double inner_tol, int inner_iters) {
+  std::vector<double> inner_tolv(b.ncol, inner_tol);
+  PrecFn K = [&](Vec& z, Vec& r, Counters& c) {
+    int e = vec_zero(z);
+    if (e) return e;
+    Counters inner;
+    const int ri = bicgstab_mixed(bl, g, M_hi, M_lo, plo, z, r, inner_tolv, inner_iters, delta, inner, M_fused);
+    if (ri != LQ_OK && ri != LQ_ENOCONV) return ri;
+    c.iters += inner.iters;
+    return 0;
+  };
+  Counters outer;
+  const int rs = fgcr(bl, g, M_hi, K, x, b, tol_in, maxiter, outer, kmax, "gcr");
+  cnt.iters += outer.iters;
+  cnt.reliable += outer.reliable;
+  return rs;
+}
+
+// One two-level V-cycle in FP32 as the preconditioner of the outer GCR on the
+// full-lattice D (sec. 2.1, Table 2's multigrid): restrict the residual, solve
+// the coarse system D_c e_c = R r by BiCGStab (FP32 coarse operator, FP64
+// reliable updates, to coarse_tol), prolong, then nu_post minimal-residual
+// steps on the fine level: r' = r - D e, then nu_post times
+// e += omega r', r' -= omega D r' with omega = <D r', r'> / |D r'|^2 per column.
+struct MgCycle {
+  OpEnv& env;
+  const MgHier& h;
+  Blas& bl;  // fine-level reductions (full lattice)
+  int n;
+  Vec r32, e32, t32, u32, bc, xc;
+  Blas blc;
+  State st;
+  Counters coarse;
+  int cycles = 0;
+  MgCycle(OpEnv& en, const MgHier& hh, Blas& b, int ncol) : env(en), h(hh), bl(b), n(ncol), st(ncol, en.s) {}
+  int init() {
+    const Geom& g = env.f->g;
+    hipStream_t s = env.s;
+    r32 = make_vec(g, 32, 12, n, 2, 0, s);
+    e32 = make_vec(g, 32, 12, n, 2, 0, s);
+    t32 = make_vec(g, 32, 12, n, 2, 0, s);
+    u32 = make_vec(g, 32, 12, n, 2, 0, s);
+    bc = make_vec(h.gc, 64, 12, n, 1, 0, s);
+    xc = make_vec(h.gc, 64, 12, n, 1, 0, s);
+    if (!r32.ok() || !e32.ok() || !t32.ok() || !u32.ok() || !bc.ok() || !xc.ok() || !st.ok())
+      return fail(LQ_ENOMEM, "multigrid cycle buffers");
+    for (int c = 0; c < n; ++c) {
+      for (int k = 0; k < ST_STRIDE; ++k) st.h(c, k) = 0.0;
+      st.h(c, ST_ACTIVE) = 1.0;
+    }
+    int e = st.push();
+    if (!e) e = blas_prepare(env.ctx, blc, h.gc, 1, n, s);
+    return e;
+  }
+  int operator()(Vec& z, Vec& r) {
+    int e = 0;
+    if ((e = vec_copy(r32, r)) || (e = mg_restrict(env, h, r32, bc)) || (e = vec_zero(xc))) return e;
+    OpFn C64 = [&](Vec& o, const Vec& i) { return mg_coarse_op(env, h, o, i); };
+    std::vector<double> tolc(n, h.coarse_tol);
+    const int rc = bicgstab_mixed(blc, h.gc, C64, C64, 32, xc, bc, tolc, h.coarse_maxiter, 0.1, coarse, nullptr);
+    if (rc != LQ_OK && rc != LQ_ENOCONV) return rc;
+    if ((e = mg_prolong(env, h, xc, e32))) return e;
+    // fine-level smoothing on the residual of the coarse correction
+    if ((e = wilson_D(env, 32, t32, e32, false)) || (e = bl.op(OP_XMY_NORM, &r32, &t32))) return e;
+    for (int k = 0; k < h.nu_post; ++k) {
+      if ((e = wilson_D(env, 32, u32, t32, false)) || (e = bl.op(OP_DOT_NORM, &u32, &t32))) return e;
+      if (launch_scalar(SC_BICG_OMEGA, bl.partial, bl.gridx, n, st.d(), env.s)) return fail(LQ_EDEVICE, "scalar");
+      if ((e = bl.op(OP_AXPY, &t32, &e32, nullptr, nullptr, nullptr, st.d(), ST_OMEGA, ST_OMEGA))) return e;
+      if (k + 1 < h.nu_post &&
+          (e = bl.op(OP_AXMY, &u32, &t32, nullptr, nullptr, nullptr, st.d(), ST_OMEGA, ST_OMEGA)))
+        return e;
+    }
+    ++cycles;
+    return vec_copy(z, e32);
+  }
+};
+
+// near-null vectors for the multigrid setup: a few passes of inverse
+// iteration w <- D^{-1} w / |D^{-1} w| from random vectors, each solve by the
+// even-odd BiCGStab in FP32 with FP64 reliable updates
+int mg_null_vectors(OpEnv& env, Vec& w, int passes, int maxiter, double tol, Counters& cnt) {
+  const Geom& g = env.f->g;
+  hipStream_t s = env.s;
+  const int n = w.ncol;
+  Vec x = make_vec(g, 64, 12, n, 2, 0, s);
+  Vec bh = make_vec(g, 64, 12, n, 1, 0, s), xe = make_vec(g, 64, 12, n, 1, 0, s);
+  Vec to64 = make_vec(g, 64, 12, n, 1, 1, s), to32 = make_vec(g, 32, 12, n, 1, 1, s);
+  if (!x.ok() || !bh.ok() || !xe.ok() || !to64.ok() || !to32.ok()) return fail(LQ_ENOMEM, "multigrid setup buffers");
+  Blas ble, bl;
+  int e = blas_prepare(env.ctx, ble, g, 1, n, s);
+  if (!e) e = blas_prepare(env.ctx, bl, g, 2, n, s);
+  if (e) return e;
+  OpFn M64 = [&](Vec& o, const Vec& i) { return tm_schur(env, 64, o, i, to64); };
+  OpFn M32 = [&](Vec& o, const Vec& i) { return tm_schur(env, 32, o, i, to32); };
+  FusedFn Mf = [&](Vec& o, const Vec& i, int mode, double* red) { return tm_schur(env, 32, o, i, to32, mode, red); };
+  State st(n, s);
+  if (!st.ok()) return fail(LQ_ENOMEM, "multigrid setup state");
+  std::vector<double> tolv(n, tol), nn;
+  for (int p = 0; p < passes; ++p) {
+    if ((e = tm_schur_source(env, bh, w)) || (e = vec_zero(xe))) return e;
+    const int rs = bicgstab_mixed(ble, g, M64, M32, 32, xe, bh, tolv, maxiter, 0.1, cnt, &Mf);
+    if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
+    if ((e = tm_schur_reconstruct(env, x, xe, w)) || (e = col_norms(bl, x, nn))) return e;
+    for (int c = 0; c < n; ++c) {
+      if (!(nn[c] > 0) || !std::isfinite(nn[c])) return fail(LQ_ENUMERIC, "multigrid setup: vanishing vector");
+      for (int k = 0; k < ST_STRIDE; ++k) st.h(c, k) = 0.0;
+      st.h(c, ST_AUX) = 1.0 / std::sqrt(nn[c]);
+    }
+    if ((e = st.push()) || (e = bl.op(OP_SCALE, &x, nullptr, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)) ||
+        (e = vec_copy(w, x)))
+      return e;
+  }
+  return 0;
 }
 
 }  // namespace
@@ -991,7 +1108,30 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
       return wilson_D(env, 64, o, i, false);
     };
     std::vector<double> res;
-    if (kind == LQ_TM_CLOVER && prm->solver != 1) {
+    if (prm->solver == 3) {
+      // flexible GCR on the full lattice, one multigrid V-cycle per direction
+      MgHier* h = f->mg;
+      if (!mg_matches(h, act)) return fail(LQ_EINVAL, "solver 3 needs lq_mg_setup for this action on this field");
+      MgCycle K(env, *h, bl, n_rhs);
+      if ((e = K.init())) return e;
+      PrecFn P = [&](Vec& z, Vec& r, Counters&) { return K(z, r); };
+      std::vector<double> tol_v(n_rhs, 0.5 * tol);
+      for (int pass = 0; pass < 4; ++pass) {
+        int steps = 0;
+        const int rs = fgcr(bl, g, D64, P, x, b, tol_v, maxiter, cnt, h->gcr_kmax, "mg-gcr", &steps);
+        if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
+        cnt.iters += steps;
+        if ((e = rel_residual(bl, D64, x, b, res, g))) return e;
+        worst = *std::max_element(res.begin(), res.end());
+        status = rs;
+        if (verbose())
+          fprintf(stderr, "[lq] multigrid solve: %d outer steps, %d coarse iterations, residual %.3e\n", steps,
+                  K.coarse.iters, worst);
+        if (worst <= tol || rs == LQ_ENOCONV) break;
+        for (int k = 0; k < n_rhs; ++k)
+          if (res[k] > tol) tol_v[k] *= std::max(0.05, 0.5 * tol / res[k]);
+      }
+    } else if (kind == LQ_TM_CLOVER && prm->solver != 1) {
       Vec bh = make_vec(g, 64, 12, n_rhs, 1, 0, s);
       Vec xe = make_vec(g, 64, 12, n_rhs, 1, 0, s);
       Vec to64 = make_vec(g, 64, 12, n_rhs, 1, 1, s);
@@ -1584,6 +1724,69 @@ int hw_bounds(lq_ctx* c, const lq_action* act, lq_field* f, int iters, double* l
   if (e) return e;
   *lmin = std::sqrt(std::max(sp.theta_min - sp.r_min, 0.0));
   *lmax = std::sqrt(sp.theta_max + sp.r_max);
+  return 0;
+}
+
+// ------------------------------------------------------------------ multigrid setup
+int mg_setup(lq_ctx* c, const lq_action* act, lq_field* f, const lq_mg_params* mp, lq_stats* st, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!mp) return fail(LQ_EINVAL, "multigrid parameters are NULL");
+  if (f->type != 0) return fail(LQ_EINVAL, "multigrid needs a Wilson gauge field");
+  if (act->kind != LQ_TM_CLOVER) return fail(LQ_EINVAL, "multigrid is implemented for the twisted-clover action");
+  const Geom& g = f->g;
+  const int nv = mp->n_vec > 0 ? mp->n_vec : 24;
+  if (nv % 6 != 0 || nv > 30) return fail(LQ_EINVAL, "n_vec must be 6, 12, 18, 24 or 30");
+  for (int mu = 0; mu < 4; ++mu) {
+    const int b = mp->block[mu];
+    if (b < 2 || g.L[mu] % b != 0 || (g.L[mu] / b) % 2 != 0)
+      return fail(LQ_EINVAL, "block extents must be >= 2 and divide the lattice into an even number of aggregates");
+  }
+  OpEnv env{c, f, *act, s};
+  Counters cnt;
+  Vec w = make_vec(g, 64, 12, nv, 2, 0, s);
+  if (!w.ok()) return fail(LQ_ENOMEM, "multigrid setup vectors");
+  int e = 0;
+  if (mp->null_vecs) {
+    const size_t bytes = (size_t)nv * 2 * g.Vh * 24 * sizeof(double);
+    DBuf aos(bytes, s);
+    if (!aos.p) return fail(LQ_ENOMEM, "multigrid setup vectors");
+    if (hipMemcpyAsync(aos.p, mp->null_vecs, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(LQ_EDEVICE, "copy");
+    if (launch_pack_field(g, aos.as<double>(), nv, 12, w.f, 64, 2, s)) return fail(LQ_EDEVICE, "pack");
+  } else {
+    if (launch_mg_random(w.f, nv, mp->seed, s)) return fail(LQ_EDEVICE, "multigrid random vectors");
+    const int passes = mp->setup_passes > 0 ? mp->setup_passes : 2;
+    const int maxiter = mp->setup_maxiter > 0 ? mp->setup_maxiter : 200;
+    const double tol = mp->setup_tol > 0 ? mp->setup_tol : 1e-4;
+    if ((e = mg_null_vectors(env, w, passes, maxiter, tol, cnt))) return e;
+  }
+  auto* h = new MgHier;
+  h->kind = act->kind;
+  h->m = act->m;
+  h->mu = act->mu;
+  h->csw = act->c_sw;
+  h->coarse_tol = mp->coarse_tol > 0 ? mp->coarse_tol : 0.1;
+  h->coarse_maxiter = mp->coarse_maxiter > 0 ? mp->coarse_maxiter : 100;
+  h->nu_post = mp->nu_post > 0 ? mp->nu_post : 4;
+  h->gcr_kmax = mp->gcr_kmax > 0 ? mp->gcr_kmax : 16;
+  if ((e = mg_init_maps(*h, g, mp->block, nv)) || (e = mg_build(env, *h, w))) {
+    mg_release(h);
+    return e;
+  }
+  h->setup_iters = cnt.iters;
+  h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  {
+    std::lock_guard<std::mutex> lk(f->mtx);
+    mg_release(f->mg);
+    f->mg = h;
+  }
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->iters = h->setup_iters;
+    st->n_apply = env.n_apply;
+    st->seconds = h->setup_seconds;
+    st->status = LQ_OK;
+  }
   return 0;
 }
 

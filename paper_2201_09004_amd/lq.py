@@ -28,7 +28,7 @@ LQ_PREC_RECON12 = 0x100
 EXPORTS = [
     "lq_init", "lq_finalize", "lq_last_error", "lq_version", "lq_gauge_load", "lq_gauge_load_dev",
     "lq_hisq_load", "lq_hisq_load_dev", "lq_field_free", "lq_apply", "lq_apply_dev", "lq_apply_noalloc", "lq_solve",
-    "lq_solve_dev", "lq_eigs", "lq_hw_bounds", "lq_cheb_coeffs", "lq_copy_bandwidth", "lq_profile", "lq_profile_get",
+    "lq_solve_dev", "lq_eigs", "lq_mg_setup", "lq_mg_apply", "lq_hw_bounds", "lq_cheb_coeffs", "lq_copy_bandwidth", "lq_profile", "lq_profile_get",
     "lq_profile_bytes",
     "lq_server_create", "lq_server_destroy", "lq_submit", "lq_poll", "lq_wait", "lq_server_stats",
 ]
@@ -55,6 +55,13 @@ class lq_params(C.Structure):
                 ("reliable_delta", C.c_double), ("n_shift", C.c_int32), ("masses", C.POINTER(C.c_double)),
                 ("reconstruct_full", C.c_int32), ("recon12", C.c_int32), ("use_initial_guess", C.c_int32),
                 ("fault_inject", C.c_int32), ("solver", C.c_int32), ("deflate", C.c_int32)]
+
+
+class lq_mg_params(C.Structure):
+    _fields_ = [("block", C.c_int32 * 4), ("n_vec", C.c_int32), ("setup_passes", C.c_int32),
+                ("setup_maxiter", C.c_int32), ("coarse_maxiter", C.c_int32), ("setup_tol", C.c_double),
+                ("coarse_tol", C.c_double), ("seed", C.c_uint64), ("null_vecs", C.POINTER(C.c_double)),
+                ("nu_post", C.c_int32), ("gcr_kmax", C.c_int32)]
 
 
 class lq_stats(C.Structure):
@@ -104,6 +111,8 @@ def load():
         "lq_hw_bounds": ([P, C.POINTER(lq_action), P, C.c_int, D, D], C.c_int),
         "lq_eigs": ([P, C.POINTER(lq_action), P, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_double, D,
                      C.POINTER(lq_stats)], C.c_int),
+        "lq_mg_setup": ([P, C.POINTER(lq_action), P, C.POINTER(lq_mg_params), C.POINTER(lq_stats)], C.c_int),
+        "lq_mg_apply": ([P, C.POINTER(lq_action), P, C.c_int, C.c_int, C.c_int, P, P], C.c_int),
         "lq_cheb_coeffs": ([C.c_double, C.c_double, C.c_int, D], C.c_int),
         "lq_copy_bandwidth": ([P, C.c_size_t, C.c_int, D], C.c_int),
         "lq_profile": ([P, C.c_int], C.c_int),
@@ -290,6 +299,37 @@ def lq_eigs(ctx, act, field, which, nev, tol=1e-10, max_restarts=0, filter_degre
                           ev.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st))
     _check(code, ok=(LQ_OK, LQ_ENOCONV))
     return ev, st.as_dict()
+
+
+LQ_MG_RESTRICT, LQ_MG_PROLONG, LQ_MG_COARSE = 0, 1, 2
+
+
+def mg_params(block=(4, 4, 4, 4), n_vec=24, setup_passes=0, setup_maxiter=0, setup_tol=0.0, coarse_tol=0.0,
+              coarse_maxiter=0, nu_post=0, gcr_kmax=0, seed=1, null_vecs=None):
+    p = lq_mg_params(n_vec=n_vec, setup_passes=setup_passes, setup_maxiter=setup_maxiter,
+                     coarse_maxiter=coarse_maxiter, setup_tol=setup_tol, coarse_tol=coarse_tol, seed=seed,
+                     nu_post=nu_post, gcr_kmax=gcr_kmax)
+    p.block[:] = list(block)
+    if null_vecs is not None:
+        arr = np.ascontiguousarray(null_vecs, dtype=np.complex128)
+        p._keep = arr
+        p.null_vecs = arr.ctypes.data_as(C.POINTER(C.c_double))
+    return p
+
+
+def lq_mg_setup(ctx, act, field, mp):
+    """Multigrid hierarchy for (field, act), kept with the field; returns the stats dict."""
+    st = lq_stats()
+    _check(load().lq_mg_setup(ctx, C.byref(act), field, C.byref(mp), C.byref(st)))
+    return st.as_dict()
+
+
+def lq_mg_apply(ctx, act, field, op, prec_bits, inp, out_shape):
+    """Restriction, prolongation or coarse operator of the stored hierarchy on host arrays."""
+    inp = np.ascontiguousarray(inp, dtype=np.complex128)
+    out = np.zeros(out_shape, dtype=np.complex128)
+    _check(load().lq_mg_apply(ctx, C.byref(act), field, op, prec_bits, inp.shape[0], _ptr(inp), _ptr(out)))
+    return out
 
 
 def lq_hw_bounds(ctx, act, field, iters=200):

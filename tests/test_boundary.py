@@ -58,6 +58,36 @@ def test_struct_layouts_match_header(lib):
     assert C.sizeof(L.lq_geom) == 20
     assert C.sizeof(L.lq_action) == 80
     assert C.sizeof(L.lq_stats) == 48
+    assert C.sizeof(L.lq_mg_params) == 72
+
+
+def test_struct_layouts_match_the_c_compiler(lib, tmp_path):
+    """Every field offset and struct size of the binding equals what gcc makes
+    of include/lq.h."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = [L.lq_geom, L.lq_action, L.lq_params, L.lq_stats, L.lq_mg_params]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lq.h"', "int main(void) {"]
+    for S in structs:
+        n = S.__name__
+        lines.append(f'printf("{n} %zu\\n", sizeof({n}));')
+        for f, _ in S._fields_:
+            lines.append(f'printf("{n}.{f} %zu\\n", offsetof({n}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    for S in structs:
+        n = S.__name__
+        assert int(got[n]) == C.sizeof(S), n
+        for f, _ in S._fields_:
+            assert int(got[f"{n}.{f}"]) == getattr(S, f).offset, (n, f)
 
 
 def test_init_without_device_is_an_error_not_a_crash(lib):
