@@ -280,7 +280,7 @@ typedef struct {
   uint64_t seed;           /* random start vectors (splitmix64 of seed and element index) */
   const double *null_vecs; /* optional host [n_vec][V][4][3]: the near-null vectors themselves, no passes */
   int32_t nu_post;         /* minimal-residual smoothing steps on the fine level (0: 4) */
-  int32_t gcr_kmax;        /* outer flexible GCR restart length (0: 16) */
+  int32_t gcr_kmax;        /* outer flexible GCR restart length (0: 8) */
 } lq_mg_params;
 
 /* Computes and stores the hierarchy.  stats: iters = setup BiCGStab iterations,

@@ -91,14 +91,18 @@ struct MgHier {
   double m = 0, mu = 0, csw = 0;  // action the hierarchy was built for
   int block[4] = {0, 0, 0, 0}, Lc[4] = {0, 0, 0, 0};
   int Vc = 0, B = 0, nv = 0, K = 0;
-  int *fine = nullptr, *nbr = nullptr, *face = nullptr, *cpar = nullptr;
+  int *fine = nullptr, *nbr = nullptr, *face = nullptr, *cpar = nullptr, *cmap = nullptr, *csite = nullptr;
+  std::vector<int> cmap_h;  // host copy of cmap
   void *Q64 = nullptr, *Q32 = nullptr, *Dc64 = nullptr, *Dc32 = nullptr;
-  Geom gc{};  // shape of coarse vectors: Vh = K * Vc pseudo-sites, one "parity"
+  // A^{-1} (direction 0) and A^{-1} Dc[d] (d = 1..8) of every aggregate: the
+  // even-odd preconditioned coarse operator
+  void *Ahat64 = nullptr, *Ahat32 = nullptr;
+  Geom gc{};  // shape of coarse vectors: Vh = K * Vc / 2 pseudo-sites per coarse parity
   double coarse_tol = 0.1;
-  int coarse_maxiter = 100, nu_post = 4, gcr_kmax = 16;
+  int coarse_maxiter = 100, nu_post = 4, gcr_kmax = 8;
   double setup_seconds = 0;
   int setup_iters = 0;
-  MgGeom geom() const { return MgGeom{Vc, B, nv, K, fine, nbr, face, cpar}; }
+  MgGeom geom() const { return MgGeom{Vc, B, nv, K, fine, nbr, face, cpar, cmap, csite}; }
 };
 
 }  // namespace lq
@@ -215,8 +219,8 @@ int tm_site(OpEnv& e, int prec, Vec& out, const Vec& in, bool inverse);
 // red_mode 2: the partials of <out, in> and |out|^2 are written to red as
 // [col][64-site tiles of Vh][4] by the second stencil (EPI_XMY_RTS)
 int tm_schur(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o, int red_mode = 0, double* red = nullptr);
-int tm_schur_source(OpEnv& e, Vec& bhat_e, const Vec& b);                 // FP64
-int tm_schur_reconstruct(OpEnv& e, Vec& x, const Vec& x_e, const Vec& b); // FP64, x full
+int tm_schur_source(OpEnv& e, Vec& bhat_e, const Vec& b);                 // in b's precision
+int tm_schur_reconstruct(OpEnv& e, Vec& x, const Vec& x_e, const Vec& b); // x full; all in x's precision
 // overlap
 int hw_apply(OpEnv& e, int prec, Vec& out, const Vec& in);
 int sign_apply(OpEnv& e, int prec, Vec& out, const Vec& in);
@@ -278,6 +282,11 @@ void mg_release(MgHier* h);
 int mg_restrict(OpEnv& e, const MgHier& h, const Vec& fine, Vec& coarse);
 int mg_prolong(OpEnv& e, const MgHier& h, const Vec& coarse, Vec& fine);
 int mg_coarse_op(OpEnv& e, const MgHier& h, Vec& out, const Vec& in);
+// even-odd coarse system: bhat_e = A_ee^-1 (b_e - D_eo A_oo^-1 b_o) with t_o = A_oo^-1 b_o kept,
+// out_e = (1 - A_ee^-1 D_eo A_oo^-1 D_oe) in_e, x_o = t_o - A_oo^-1 D_oe x_e (x full, x_e copied in)
+int mg_schur_source(OpEnv& e, const MgHier& h, Vec& bhat_e, Vec& t_o, Vec& u_e, const Vec& b);
+int mg_schur_op(OpEnv& e, const MgHier& h, Vec& out_e, const Vec& in_e, Vec& tmp_o);
+int mg_schur_reconstruct(OpEnv& e, const MgHier& h, Vec& x, const Vec& x_e, const Vec& t_o);
 int mg_apply_host(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec, int n_rhs, const double* in,
                   double* out, hipStream_t s);
 int mg_setup(lq_ctx* c, const lq_action* act, lq_field* f, const lq_mg_params* mp, lq_stats* st, hipStream_t s);

@@ -150,16 +150,23 @@ int launch_ms_init(const MsArgs& A, hipStream_t s);
 // Q[Vc][B][2][nv][6], coarse operator Dc[Vc][9][2nv][2nv] (see mg.hip).
 struct MgGeom {
   int Vc, B, nv, K;
-  const int* fine;  // [Vc * B]: fine site cb | parity << 30 of (aggregate, in-block index)
-  const int* nbr;   // [Vc][8]: aggregate at Y + mu (2 mu) and Y - mu (2 mu + 1)
-  const int* face;  // [Vc * B]: bit 2 mu: lowest layer in mu, bit 2 mu + 1: highest layer
-  const int* cpar;  // [Vc]: coarse coordinate parities, bit mu = Y_mu & 1
+  const int* fine;   // [Vc * B]: fine site cb | parity << 30 of (aggregate, in-block index)
+  const int* nbr;    // [Vc][8]: aggregate at Y + mu (2 mu) and Y - mu (2 mu + 1)
+  const int* face;   // [Vc * B]: bit 2 mu: lowest layer in mu, bit 2 mu + 1: highest layer
+  const int* cpar;   // [Vc]: coarse coordinate parities, bit mu = Y_mu & 1
+  const int* cmap;   // [Vc]: coarse checkerboard index | coarse parity << 30
+  const int* csite;  // [2][Vc / 2]: aggregate of (parity, checkerboard index)
 };
 int launch_mg_restrict(const MgGeom& m, int pf, const void* Q, FieldRef fine, int pc, FieldRef coarse, int ncol,
                        hipStream_t s);
 int launch_mg_prolong(const MgGeom& m, int pc, FieldRef coarse, int pf, const void* Q, FieldRef fine, int ncol,
                       hipStream_t s);
-int launch_mg_coarse(const MgGeom& m, int p, const void* Dc, FieldRef in, FieldRef out, int ncol, hipStream_t s);
+// out(Y) = a x(Y) + sgn sum_{d0 <= d < d0 + nd} M[Y][d] in(N_d(Y)) on the aggregates of parity par_out (2: all)
+int launch_mg_stencil(const MgGeom& m, int p, const void* M, int d0, int nd, FieldRef in, FieldRef out, FieldRef x,
+                      double a, double sgn, int par_out, int ncol, hipStream_t s);
+// Ahat[Y][0] = Dc[Y][0]^{-1} (FP64; work: Vc * 2 (2 nv)^2 complex), then Ahat[Y][d] = Ahat[Y][0] Dc[Y][d], d = 1..8
+int launch_mg_site_inverse(const MgGeom& m, const void* Dc64, void* Ahat64, void* work, int* bad, hipStream_t s);
+int launch_mg_site_mul(const MgGeom& m, const void* Dc64, void* Ahat64, hipStream_t s);
 int launch_mg_gather(const MgGeom& m, FieldRef fine, void* Q64, hipStream_t s);
 int launch_mg_orth(const MgGeom& m, void* Q64, int* bad, hipStream_t s);
 int launch_mg_probe_source(const MgGeom& m, FieldRef coarse, int ncol, int k0, int cls, hipStream_t s);

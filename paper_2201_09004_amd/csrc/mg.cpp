@@ -48,7 +48,8 @@ void* dev_alloc(size_t bytes) {
 
 void mg_release(MgHier* h) {
   if (!h) return;
-  for (void* p : {(void*)h->fine, (void*)h->nbr, (void*)h->face, (void*)h->cpar, h->Q64, h->Q32, h->Dc64, h->Dc32})
+  for (void* p : {(void*)h->fine, (void*)h->nbr, (void*)h->face, (void*)h->cpar, (void*)h->cmap, (void*)h->csite,
+                  h->Q64, h->Q32, h->Dc64, h->Dc32, h->Ahat64, h->Ahat32})
     if (p) hipFree(p);
   delete h;
 }
@@ -70,7 +71,9 @@ int mg_init_maps(MgHier& h, const Geom& g, const int block[4], int nv) {
     h.Vc *= h.Lc[mu];
   }
   std::vector<int> fine((size_t)h.Vc * h.B), face((size_t)h.Vc * h.B), nbr((size_t)h.Vc * 8), cpar(h.Vc);
+  std::vector<int> cmap(h.Vc), csite(h.Vc);
   const int* Lc = h.Lc;
+  int ncb[2] = {0, 0};
   for (int Y = 0; Y < h.Vc; ++Y) {
     int yc[4];
     int r = Y;
@@ -79,6 +82,10 @@ int mg_init_maps(MgHier& h, const Geom& g, const int block[4], int nv) {
       r /= Lc[mu];
     }
     cpar[Y] = (yc[0] & 1) | (yc[1] & 1) << 1 | (yc[2] & 1) << 2 | (yc[3] & 1) << 3;
+    const int cp = (yc[0] + yc[1] + yc[2] + yc[3]) & 1;
+    const int cb = ncb[cp]++;
+    cmap[Y] = cb | cp << 30;
+    csite[cp * (h.Vc / 2) + cb] = Y;
     for (int mu = 0; mu < 4; ++mu)
       for (int sgn = 0; sgn < 2; ++sgn) {
         int zc[4] = {yc[0], yc[1], yc[2], yc[3]};
@@ -109,9 +116,13 @@ int mg_init_maps(MgHier& h, const Geom& g, const int block[4], int nv) {
   if (!e) e = upload_ints(&h.face, face, s);
   if (!e) e = upload_ints(&h.nbr, nbr, s);
   if (!e) e = upload_ints(&h.cpar, cpar, s);
+  if (!e) e = upload_ints(&h.cmap, cmap, s);
+  if (!e) e = upload_ints(&h.csite, csite, s);
   if (e) return e;
+  if (ncb[0] != h.Vc / 2 || ncb[1] != h.Vc / 2) return fail(LQ_EINVAL, "multigrid: odd coarse lattice");
+  h.cmap_h = cmap;
   h.gc = g;
-  h.gc.Vh = h.K * h.Vc;
+  h.gc.Vh = h.K * h.Vc / 2;
   return 0;
 }
 
@@ -139,7 +150,7 @@ int mg_build(OpEnv& e, MgHier& h, Vec& vecs) {
   if (nbad) return fail(LQ_ENUMERIC, "multigrid: a near-null vector vanishes on an aggregate");
   // probing, 12 coarse components at a time
   const int nb = std::min(12, n2);
-  Vec pc = make_vec(h.gc, 64, 12, nb, 1, 0, s);
+  Vec pc = make_vec(h.gc, 64, 12, nb, 2, 0, s);
   Vec pf = make_vec(e.f->g, 64, 12, nb, 2, 0, s);
   Vec df = make_vec(e.f->g, 64, 12, nb, 2, 0, s);
   if (!pc.ok() || !pf.ok() || !df.ok()) return fail(LQ_ENOMEM, "multigrid probes");
@@ -155,7 +166,18 @@ int mg_build(OpEnv& e, MgHier& h, Vec& vecs) {
       if (launch_mg_probe_restrict(m, h.Q64, dfw.f, w, k0, cls, h.Dc64, s)) return fail(LQ_EDEVICE, "multigrid probe");
     }
   if (launch_mg_narrow(h.Dc64, h.Dc32, (int64_t)nd, s)) return fail(LQ_EDEVICE, "multigrid coarse operator");
-  if (hipStreamSynchronize(s) != hipSuccess) return fail(LQ_EDEVICE, "multigrid setup");
+  // the even-odd preconditioned coarse operator: A^{-1} and A^{-1} Dc[d]
+  h.Ahat64 = dev_alloc(nd * 16);
+  h.Ahat32 = dev_alloc(nd * 8);
+  DBuf work((size_t)h.Vc * n2 * 2 * n2 * 16, s);
+  if (!h.Ahat64 || !h.Ahat32 || !work.p) return fail(LQ_ENOMEM, "multigrid coarse operator");
+  if (launch_fill_zero(bad.p, sizeof(int), s) || launch_mg_site_inverse(m, h.Dc64, h.Ahat64, work.p, bad.as<int>(), s) ||
+      launch_mg_site_mul(m, h.Dc64, h.Ahat64, s) || launch_mg_narrow(h.Ahat64, h.Ahat32, (int64_t)nd, s))
+    return fail(LQ_EDEVICE, "multigrid coarse operator");
+  if (hipMemcpyAsync(&nbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(LQ_EDEVICE, "multigrid setup");
+  if (nbad) return fail(LQ_ENUMERIC, "multigrid: singular self block of the coarse operator");
   return 0;
 }
 
@@ -184,9 +206,46 @@ int mg_coarse_op(OpEnv& e, const MgHier& h, Vec& out, const Vec& in) {
   Prof p(e.ctx, in.prec == 64 ? "mg_coarse64" : "mg_coarse32", e.s, bytes);
   e.n_apply += 1;
   e.bytes += bytes;
-  return launch_mg_coarse(h.geom(), in.prec, in.prec == 64 ? h.Dc64 : h.Dc32, in.f, out.f, in.ncol, e.s)
+  return launch_mg_stencil(h.geom(), in.prec, in.prec == 64 ? h.Dc64 : h.Dc32, 0, 9, in.f, out.f, in.f, 0.0, 1.0, 2,
+                           in.ncol, e.s)
              ? fail(LQ_EDEVICE, "multigrid coarse operator")
              : 0;
+}
+
+namespace {
+// one launch of the coarse stencil on half the aggregates, timed as mg_hop<P>
+int hop_half(OpEnv& e, const MgHier& h, int prec, int d0, int nd, const Vec& in, Vec& out, const Vec& x, double a,
+             double sgn, int par_out) {
+  const int n2 = 2 * h.nv;
+  const double bytes = (double)h.Vc / 2 * nd * n2 * n2 * (prec == 64 ? 16 : 8) +
+                       (2.0 + (a != 0.0)) * h.Vc / 2 * n2 * in.ncol * (prec == 64 ? 16 : 8);
+  Prof p(e.ctx, prec == 64 ? "mg_hop64" : "mg_hop32", e.s, bytes);
+  e.bytes += bytes;
+  return launch_mg_stencil(h.geom(), prec, prec == 64 ? h.Ahat64 : h.Ahat32, d0, nd, in.f, out.f, x.f, a, sgn, par_out,
+                           in.ncol, e.s)
+             ? fail(LQ_EDEVICE, "multigrid coarse stencil")
+             : 0;
+}
+}  // namespace
+
+int mg_schur_source(OpEnv& e, const MgHier& h, Vec& bhat_e, Vec& t_o, Vec& u_e, const Vec& b) {
+  int r = hop_half(e, h, b.prec, 0, 1, b, t_o, b, 0.0, 1.0, 1);          // t_o = A_oo^-1 b_o
+  if (!r) r = hop_half(e, h, b.prec, 1, 8, t_o, u_e, t_o, 0.0, 1.0, 0);  // u_e = A_ee^-1 D_eo t_o
+  if (!r) r = hop_half(e, h, b.prec, 0, 1, b, bhat_e, u_e, -1.0, 1.0, 0);  // A_ee^-1 b_e - u_e
+  return r;
+}
+
+int mg_schur_op(OpEnv& e, const MgHier& h, Vec& out_e, const Vec& in_e, Vec& tmp_o) {
+  e.n_apply += 1;
+  int r = hop_half(e, h, in_e.prec, 1, 8, in_e, tmp_o, in_e, 0.0, 1.0, 1);
+  if (!r) r = hop_half(e, h, in_e.prec, 1, 8, tmp_o, out_e, in_e, 1.0, -1.0, 0);
+  return r;
+}
+
+int mg_schur_reconstruct(OpEnv& e, const MgHier& h, Vec& x, const Vec& x_e, const Vec& t_o) {
+  int r = hop_half(e, h, x.prec, 0, 0, x_e, x, x_e, 1.0, 1.0, 0);           // x_e into x
+  if (!r) r = hop_half(e, h, x.prec, 1, 8, x_e, x, t_o, 1.0, -1.0, 1);      // x_o = t_o - A_oo^-1 D_oe x_e
+  return r;
 }
 
 // ------------------------------------------------------------------ host arrays
@@ -202,7 +261,9 @@ int coarse_to_host(const MgHier& h, const Vec& v, double* out, hipStream_t s) {
   for (int col = 0; col < v.ncol; ++col)
     for (int Y = 0; Y < h.Vc; ++Y)
       for (int d = 0; d < n2; ++d) {
-        const int64_t i = tix(col, d % 12, 12, Y * h.K + d / 12, h.gc.Vh);
+        const int cm = h.cmap_h[Y];
+        const int64_t i = tix((int64_t)col * 2 + ((cm >> 30) & 1), d % 12, 12, (cm & 0x3fffffff) * h.K + d / 12,
+                              h.gc.Vh);
         double* o = out + 2 * (((int64_t)col * h.Vc + Y) * n2 + d);
         o[0] = raw[2 * i];
         o[1] = raw[2 * i + 1];
@@ -216,7 +277,9 @@ int coarse_from_host(const MgHier& h, Vec& v, const double* in, hipStream_t s) {
   for (int col = 0; col < v.ncol; ++col)
     for (int Y = 0; Y < h.Vc; ++Y)
       for (int d = 0; d < n2; ++d) {
-        const int64_t i = tix(col, d % 12, 12, Y * h.K + d / 12, h.gc.Vh);
+        const int cm = h.cmap_h[Y];
+        const int64_t i = tix((int64_t)col * 2 + ((cm >> 30) & 1), d % 12, 12, (cm & 0x3fffffff) * h.K + d / 12,
+                              h.gc.Vh);
         const double* x = in + 2 * (((int64_t)col * h.Vc + Y) * n2 + d);
         raw[2 * i] = x[0];
         raw[2 * i + 1] = x[1];
@@ -240,8 +303,8 @@ int mg_apply_host(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec
   OpEnv env{c, f, *act, s};
   const size_t fine_doubles = (size_t)n * 2 * g.Vh * 24;
   const size_t coarse_doubles = (size_t)n * h->Vc * 2 * h->nv * 2;
-  Vec c64 = make_vec(h->gc, 64, 12, n, 1, 0, s);
-  Vec clo = make_vec(h->gc, prec, 12, n, 1, 0, s);
+  Vec c64 = make_vec(h->gc, 64, 12, n, 2, 0, s);
+  Vec clo = make_vec(h->gc, prec, 12, n, 2, 0, s);
   Vec f64 = make_vec(g, 64, 12, n, 2, 0, s);
   Vec flo = make_vec(g, prec, 12, n, 2, 0, s);
   DBuf aos(sizeof(double) * std::max(fine_doubles, coarse_doubles), s);
@@ -263,7 +326,7 @@ int mg_apply_host(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec
       return fail(LQ_EDEVICE, "copy");
     return 0;
   }
-  Vec olo = make_vec(h->gc, prec, 12, n, 1, 0, s);
+  Vec olo = make_vec(h->gc, prec, 12, n, 2, 0, s);
   if (!olo.ok()) return fail(LQ_ENOMEM, "multigrid buffers");
   if ((e = vec_copy(clo, c64)) || (e = mg_coarse_op(env, *h, olo, clo)) || (e = vec_copy(c64, olo))) return e;
   return coarse_to_host(*h, c64, out, s);

@@ -16,6 +16,8 @@
 // Dc[Vc][9][n2 (column k)][n2 (row i)]: direction 0 is the aggregate itself,
 // 1 + 2 mu couples to Y + mu and 2 + 2 mu to Y - mu; rows are contiguous so
 // that the threads of a coarse site read a column in one pass.
+#include <cstdlib>
+
 #include "lq_common.h"
 #include "lq_kernels.h"
 
@@ -27,33 +29,41 @@ template <int P> struct CxT;
 template <> struct CxT<64> { using T = double2; using R = double; };
 template <> struct CxT<32> { using T = float2; using R = float; };
 
-// one complex number of a coarse vector
+// one complex number of a coarse vector, at pseudo-site q of block blk
 template <int P> struct CIO;
 template <> struct CIO<64> {
-  static __device__ __forceinline__ cx<double> ld(const FieldRef& f, int col, int q, int c) {
-    const double2 v = ((const double2*)f.data)[tix(col, c, 12, q, f.Vh)];
+  static __device__ __forceinline__ cx<double> ld(const FieldRef& f, int64_t blk, int q, int c) {
+    const double2 v = ((const double2*)f.data)[tix(blk, c, 12, q, f.Vh)];
     return {v.x, v.y};
   }
-  static __device__ __forceinline__ void st(const FieldRef& f, int col, int q, int c, cx<double> v) {
-    ((double2*)f.data)[tix(col, c, 12, q, f.Vh)] = make_double2(v.re, v.im);
+  static __device__ __forceinline__ void st(const FieldRef& f, int64_t blk, int q, int c, cx<double> v) {
+    ((double2*)f.data)[tix(blk, c, 12, q, f.Vh)] = make_double2(v.re, v.im);
   }
 };
 template <> struct CIO<32> {
-  static __device__ __forceinline__ cx<float> ld(const FieldRef& f, int col, int q, int c) {
-    const float2 v = ((const float2*)f.data)[2 * tix(col, c >> 1, 6, q, f.Vh) + (c & 1)];
+  static __device__ __forceinline__ cx<float> ld(const FieldRef& f, int64_t blk, int q, int c) {
+    const float2 v = ((const float2*)f.data)[2 * tix(blk, c >> 1, 6, q, f.Vh) + (c & 1)];
     return {v.x, v.y};
   }
-  static __device__ __forceinline__ void st(const FieldRef& f, int col, int q, int c, cx<float> v) {
-    ((float2*)f.data)[2 * tix(col, c >> 1, 6, q, f.Vh) + (c & 1)] = make_float2(v.re, v.im);
+  static __device__ __forceinline__ void st(const FieldRef& f, int64_t blk, int q, int c, cx<float> v) {
+    ((float2*)f.data)[2 * tix(blk, c >> 1, 6, q, f.Vh) + (c & 1)] = make_float2(v.re, v.im);
   }
 };
+// component d of aggregate Y in column col: the aggregate's parity block
+// (npar = 2, or the one stored parity of an npar = 1 vector) and its
+// checkerboard index, K pseudo-sites per aggregate
 template <int P>
-__device__ __forceinline__ cx<typename CxT<P>::R> cld(const FieldRef& f, int col, int Y, int d, int K) {
-  return CIO<P>::ld(f, col, Y * K + d / 12, d % 12);
+__device__ __forceinline__ cx<typename CxT<P>::R> cld(const FieldRef& f, const MgGeom& m, int col, int Y, int d) {
+  const int v = m.cmap[Y];
+  const int64_t blk = (int64_t)col * f.npar + (f.npar == 2 ? (v >> 30) & 1 : 0);
+  return CIO<P>::ld(f, blk, (v & 0x3fffffff) * m.K + d / 12, d % 12);
 }
 template <int P>
-__device__ __forceinline__ void cst(const FieldRef& f, int col, int Y, int d, int K, cx<typename CxT<P>::R> v) {
-  CIO<P>::st(f, col, Y * K + d / 12, d % 12, v);
+__device__ __forceinline__ void cst(const FieldRef& f, const MgGeom& m, int col, int Y, int d,
+                                    cx<typename CxT<P>::R> x) {
+  const int v = m.cmap[Y];
+  const int64_t blk = (int64_t)col * f.npar + (f.npar == 2 ? (v >> 30) & 1 : 0);
+  CIO<P>::st(f, blk, (v & 0x3fffffff) * m.K + d / 12, d % 12, x);
 }
 
 // the six components of chirality s of a fine Wilson site (FP64 / FP32 layouts)
@@ -136,7 +146,7 @@ __global__ void __launch_bounds__(64) mg_restrict_kernel(MgGeom m, const void* Q
   using RC = typename CxT<PC>::R;
 #pragma unroll
   for (int cc = 0; cc < MG_CB; ++cc)
-    if (cc < nc) cst<PC>(coarse, col0 + cc, Y, t, m.K, cx<RC>{(RC)acc[cc].re, (RC)acc[cc].im});
+    if (cc < nc) cst<PC>(coarse, m, col0 + cc, Y, t, cx<RC>{(RC)acc[cc].re, (RC)acc[cc].im});
 }
 
 // prolongation: fine(col, y)_s = sum_j coarse(col, Y(y), s nv + j) q_{Y,s,j}(y);
@@ -164,7 +174,7 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(MgGeom m, FieldRef coar
 #pragma unroll
     for (int cc = 0; cc < MG_CB; ++cc) {
       if (cc < nc) {
-        const auto a = cld<PC>(coarse, col0 + cc, Y, s * m.nv + j, m.K);
+        const auto a = cld<PC>(coarse, m, col0 + cc, Y, s * m.nv + j);
         const cx<R> ar = {(R)a.re, (R)a.im};
 #pragma unroll
         for (int c = 0; c < 6; ++c) fma(acc[cc][c], qv[c], ar);
@@ -179,31 +189,136 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(MgGeom m, FieldRef coar
 }
 
 // ---------------------------------------------------------------- coarse stencil
-// out(col, Y, i) = sum_d sum_k Dc[Y][d][k][i] in(col, N_d(Y), k); one thread per row i
-template <int P>
-__global__ void __launch_bounds__(64) mg_coarse_kernel(MgGeom m, const void* Dcv, FieldRef in, FieldRef out,
-                                                        int ncol) {
+// The generic coarse stencil over the aggregates Y of parity par_out (2: all):
+//   out(Y) = a x(Y) + sgn sum_{d = d0}^{d0 + nd - 1} M[Y][d] in(N_d(Y))
+// with M[Y][d] an (n2 x n2) block stored by columns (direction 0: the
+// aggregate itself).  One wave per aggregate, thread i = row; the input block
+// of each direction (n2 x NCB columns) is staged in LDS, so the wave streams
+// its blocks from HBM once per NCB columns.  (Prefetching the next direction's
+// block into registers measured slower: loads complete in order, so the first
+// matrix load of a direction waits for them.)
+template <int P, int NCB>
+__global__ void __launch_bounds__(64) mg_stencil_kernel(MgGeom m, const void* Mv, int d0, int nd, FieldRef in,
+                                                         FieldRef out, FieldRef x, double a, double sgn,
+                                                         int par_out, int ncol) {
   using R = typename CxT<P>::R;
-  const int Y = blockIdx.x, i = threadIdx.x, n2 = 2 * m.nv;
-  if (i >= n2) return;
-  const int col0 = blockIdx.y * MG_CB;
-  const int nc = min(MG_CB, ncol - col0);
-  cx<R> acc[MG_CB];
+  __shared__ cx<R> sin_[64 * NCB];
+  const int Y = par_out == 2 ? blockIdx.x : m.csite[par_out * (m.Vc / 2) + blockIdx.x];
+  const int i = threadIdx.x, n2 = 2 * m.nv;
+  const int col0 = blockIdx.y * NCB;
+  const int nc = min(NCB, ncol - col0);
+  cx<R> acc[NCB];
 #pragma unroll
-  for (int c = 0; c < MG_CB; ++c) acc[c] = {0, 0};
-  for (int d = 0; d < 9; ++d) {
+  for (int c = 0; c < NCB; ++c) acc[c] = {0, 0};
+  for (int d = d0; d < d0 + nd; ++d) {
     const int Yn = d == 0 ? Y : m.nbr[Y * 8 + d - 1];
-    const cx<R>* M = (const cx<R>*)Dcv + ((int64_t)Y * 9 + d) * n2 * n2 + i;
-    for (int k = 0; k < n2; ++k) {
-      const cx<R> a = M[(int64_t)k * n2];
+    __syncthreads();  // the previous direction's block is no longer read
+    for (int e = i; e < n2 * NCB; e += 64) {
+      const int k = e / NCB, cc = e - k * NCB;
+      sin_[e] = cc < nc ? cld<P>(in, m, col0 + cc, Yn, k) : cx<R>{0, 0};
+    }
+    __syncthreads();
+    if (i < n2) {
+      const cx<R>* M = (const cx<R>*)Mv + ((int64_t)Y * 9 + d) * n2 * n2 + i;
+#pragma unroll 8
+      for (int k = 0; k < n2; ++k) {
+        const cx<R> w = M[(int64_t)k * n2];
 #pragma unroll
-      for (int cc = 0; cc < MG_CB; ++cc)
-        if (cc < nc) fma(acc[cc], a, cld<P>(in, col0 + cc, Yn, k, m.K));
+        for (int cc = 0; cc < NCB; ++cc) fma(acc[cc], w, sin_[k * NCB + cc]);
+      }
     }
   }
+  if (i < n2) {
 #pragma unroll
-  for (int cc = 0; cc < MG_CB; ++cc)
-    if (cc < nc) cst<P>(out, col0 + cc, Y, i, m.K, acc[cc]);
+    for (int cc = 0; cc < NCB; ++cc) {
+      if (cc < nc) {
+        cx<R> o = {(R)sgn * acc[cc].re, (R)sgn * acc[cc].im};
+        if (a != 0.0) o = o + (R)a * cld<P>(x, m, col0 + cc, Y, i);
+        cst<P>(out, m, col0 + cc, Y, i, o);
+      }
+    }
+  }
+}
+
+// The same stencil in FP32 on the matrix cores, 12 columns per wave: per
+// direction the complex product Y = M X (n2 x n2 times n2 x 12) is the real
+// product [Mr | Mi] [[Xr, Xi], [-Xi, Xr]] = [Yr | Yi], done as
+// v_mfma_f32_16x16x4f32 steps: rows of M in 16-row tiles, the 24 real output
+// columns in two 16-column tiles (8 padding columns), k in groups of 4; the
+// real and imaginary parts of one loaded matrix element feed the Mr and the Mi
+// step of the same k.  Lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and
+// D[4 (l / 16) + i][l % 16], i = 0..3.
+typedef float mg_f4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(64) mg_stencil_mfma_kernel(MgGeom m, const void* Mv, int d0, int nd, FieldRef in,
+                                                              FieldRef out, FieldRef x, double a, double sgn,
+                                                              int par_out, int ncol) {
+  __shared__ float2 sx[64 * 12];
+  __shared__ float so[2][64][13];
+  const int Y = par_out == 2 ? blockIdx.x : m.csite[par_out * (m.Vc / 2) + blockIdx.x];
+  const int lane = threadIdx.x, r16 = lane & 15, q = lane >> 4, n2 = 2 * m.nv;
+  const int mtiles = (n2 + 15) >> 4;
+  const int col0 = blockIdx.y * 12;
+  const int nc = min(12, ncol - col0);
+  mg_f4 acc[4][2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t][0] = acc[t][1] = mg_f4{0.f, 0.f, 0.f, 0.f};
+  for (int d = d0; d < d0 + nd; ++d) {
+    const int Yn = d == 0 ? Y : m.nbr[Y * 8 + d - 1];
+    __syncthreads();
+    for (int e = lane; e < n2 * 12; e += 64) {
+      const int k = e / 12, cc = e - k * 12;
+      const cx<float> v = cc < nc ? cld<32>(in, m, col0 + cc, Yn, k) : cx<float>{0.f, 0.f};
+      sx[e] = make_float2(v.re, v.im);
+    }
+    __syncthreads();
+    const float2* M = (const float2*)Mv + ((int64_t)Y * 9 + d) * n2 * n2;
+    for (int kg = 0; kg < (n2 >> 2); ++kg) {
+      const int k = 4 * kg + q;
+      float bR[2], bI[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int n = 16 * t + r16;
+        const float2 xv = n < 24 ? sx[k * 12 + (n < 12 ? n : n - 12)] : make_float2(0.f, 0.f);
+        bR[t] = n < 12 ? xv.x : (n < 24 ? xv.y : 0.f);
+        bI[t] = n < 12 ? -xv.y : (n < 24 ? xv.x : 0.f);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < mtiles) {
+          const int row = 16 * t + r16;
+          const float2 av = row < n2 ? M[(int64_t)k * n2 + row] : make_float2(0.f, 0.f);
+          acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bR[0], acc[t][0], 0, 0, 0);
+          acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bI[0], acc[t][0], 0, 0, 0);
+          acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bR[1], acc[t][1], 0, 0, 0);
+          acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bI[1], acc[t][1], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // D tiles -> [re / im][row][column] in LDS, then one complex output per (row, column)
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t < mtiles) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int n = 16 * u + r16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * t + 4 * q + i;
+          if (n < 24 && row < 64) so[n < 12 ? 0 : 1][row][n < 12 ? n : n - 12] = acc[t][u][i];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (lane < n2) {
+    for (int cc = 0; cc < nc; ++cc) {
+      cx<float> o = {(float)sgn * so[0][lane][cc], (float)sgn * so[1][lane][cc]};
+      if (a != 0.0) o = o + (float)a * cld<32>(x, m, col0 + cc, Y, lane);
+      cst<32>(out, m, col0 + cc, Y, lane, o);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- setup
@@ -299,7 +414,7 @@ __global__ void __launch_bounds__(256) mg_probe_source_kernel(MgGeom m, FieldRef
   const int Y = (int)((gid / n2) % m.Vc);
   const int col = (int)(gid / ((int64_t)n2 * m.Vc));
   const double v = (d == k0 + col && m.cpar[Y] == cls) ? 1.0 : 0.0;
-  cst<64>(coarse, col, Y, d, m.K, cx<double>{v, 0.0});
+  cst<64>(coarse, m, col, Y, d, cx<double>{v, 0.0});
 }
 
 // Columns k0.. of Dc from D applied to the probe sources of class cls: an
@@ -379,6 +494,97 @@ __global__ void __launch_bounds__(256) mg_random_kernel(FieldRef fine, int ncol,
   }
 }
 
+// A^{-1} of every aggregate's self block A = Dc[Y][0] (FP64 Gauss-Jordan with
+// partial pivoting on [A | 1], one wave per aggregate, in a global workspace of
+// n2 x 2 n2 complex per aggregate) into Ahat[Y][0]
+__global__ void __launch_bounds__(64) mg_site_inverse_kernel(MgGeom m, const double2* Dc, double2* Ahat,
+                                                              double2* work, int* bad) {
+  const int Y = blockIdx.x, t = threadIdx.x, n2 = 2 * m.nv, w = 2 * n2;
+  double2* G = work + (int64_t)Y * n2 * w;  // [row][2 n2]
+  __shared__ int piv;
+  const double2* A = Dc + (int64_t)Y * 9 * n2 * n2;  // column k at A + k n2
+  for (int e = t; e < n2 * w; e += 64) {
+    const int r = e / w, c = e - r * w;
+    G[e] = c < n2 ? A[(int64_t)c * n2 + r] : make_double2(c - n2 == r ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < n2; ++k) {
+    if (t == 0) {
+      int p = k;
+      double best = -1.0;
+      for (int r = k; r < n2; ++r) {
+        const double2 v = G[r * w + k];
+        const double a2 = v.x * v.x + v.y * v.y;
+        if (a2 > best) {
+          best = a2;
+          p = r;
+        }
+      }
+      piv = p;
+      if (!(best > 0.0)) atomicAdd(bad, 1);
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != k)
+      for (int c = t; c < w; c += 64) {
+        const double2 u = G[k * w + c];
+        G[k * w + c] = G[p * w + c];
+        G[p * w + c] = u;
+      }
+    __syncthreads();
+    const double2 d = G[k * w + k];
+    const double dd = d.x * d.x + d.y * d.y;
+    const double2 inv = make_double2(d.x / dd, -d.y / dd);
+    __syncthreads();
+    for (int c = t; c < w; c += 64) {
+      const double2 u = G[k * w + c];
+      G[k * w + c] = make_double2(u.x * inv.x - u.y * inv.y, u.x * inv.y + u.y * inv.x);
+    }
+    __syncthreads();
+    for (int e = t; e < n2 * w; e += 64) {
+      const int r = e / w, c = e - r * w;
+      if (r == k) continue;
+      const double2 f = G[r * w + k];
+      const double2 u = G[k * w + c];
+      if (c == k) continue;  // column k of row r is cleared below, after every row has read it
+      G[r * w + c] = make_double2(G[r * w + c].x - (f.x * u.x - f.y * u.y), G[r * w + c].y - (f.x * u.y + f.y * u.x));
+    }
+    __syncthreads();
+    for (int r = t; r < n2; r += 64)
+      if (r != k) G[r * w + k] = make_double2(0.0, 0.0);
+    __syncthreads();
+  }
+  double2* out = Ahat + (int64_t)Y * 9 * n2 * n2;
+  for (int e = t; e < n2 * n2; e += 64) {
+    const int r = e / n2, c = e - r * n2;
+    out[(int64_t)c * n2 + r] = G[r * w + n2 + c];
+  }
+}
+
+// Ahat[Y][d] = A^{-1}(Y) Dc[Y][d] for the eight hops (blocks stored by columns):
+// thread i computes row i of every column
+__global__ void __launch_bounds__(64) mg_site_mul_kernel(MgGeom m, const double2* Dc, double2* Ahat) {
+  const int Y = blockIdx.x, d = 1 + blockIdx.y, i = threadIdx.x, n2 = 2 * m.nv;
+  if (i >= n2) return;
+  const double2* Ai = Ahat + (int64_t)Y * 9 * n2 * n2;          // A^{-1}, column j at Ai + j n2
+  const double2* M = Dc + ((int64_t)Y * 9 + d) * n2 * n2;        // column k at M + k n2
+  double2* C = Ahat + ((int64_t)Y * 9 + d) * n2 * n2;
+  for (int k = 0; k < n2; ++k) {
+    cx<double> acc = {0, 0};
+    for (int j = 0; j < n2; ++j) {
+      const double2 a = Ai[(int64_t)j * n2 + i], b = M[(int64_t)k * n2 + j];
+      fma(acc, cx<double>{a.x, a.y}, cx<double>{b.x, b.y});
+    }
+    C[(int64_t)k * n2 + i] = make_double2(acc.re, acc.im);
+  }
+}
+
+// the FP32 coarse stencil on the matrix cores unless LQ_MG_VALU is set
+inline bool mg_use_mfma() {
+  static const bool v = getenv("LQ_MG_VALU") == nullptr;
+  return v;
+}
+
 inline int grid_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 1 << 20); }
 
 }  // namespace
@@ -409,13 +615,29 @@ int launch_mg_prolong(const MgGeom& m, int pc, FieldRef coarse, int pf, const vo
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-int launch_mg_coarse(const MgGeom& m, int p, const void* Dc, FieldRef in, FieldRef out, int ncol, hipStream_t s) {
+int launch_mg_stencil(const MgGeom& m, int p, const void* M, int d0, int nd, FieldRef in, FieldRef out, FieldRef x,
+                      double a, double sgn, int par_out, int ncol, hipStream_t s) {
   if (ncol <= 0) return 0;
-  if (2 * m.nv > 64) return -1;
-  dim3 grid(m.Vc, (ncol + MG_CB - 1) / MG_CB), block(64);
-  if (p == 64) mg_coarse_kernel<64><<<grid, block, 0, s>>>(m, Dc, in, out, ncol);
-  else if (p == 32) mg_coarse_kernel<32><<<grid, block, 0, s>>>(m, Dc, in, out, ncol);
+  if (2 * m.nv > 64 || d0 < 0 || nd < 0 || d0 + nd > 9 || par_out < 0 || par_out > 2) return -1;
+  const bool wide = ncol > 4;
+  dim3 grid(par_out == 2 ? m.Vc : m.Vc / 2, wide ? (ncol + 11) / 12 : 1), block(64);
+  if (p == 64 && wide) mg_stencil_kernel<64, 12><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
+  else if (p == 64) mg_stencil_kernel<64, 4><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
+  else if (p == 32 && wide && mg_use_mfma())
+    mg_stencil_mfma_kernel<<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
+  else if (p == 32 && wide) mg_stencil_kernel<32, 12><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
+  else if (p == 32) mg_stencil_kernel<32, 4><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
   else return -1;
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_mg_site_inverse(const MgGeom& m, const void* Dc64, void* Ahat64, void* work, int* bad, hipStream_t s) {
+  mg_site_inverse_kernel<<<m.Vc, 64, 0, s>>>(m, (const double2*)Dc64, (double2*)Ahat64, (double2*)work, bad);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_mg_site_mul(const MgGeom& m, const void* Dc64, void* Ahat64, hipStream_t s) {
+  mg_site_mul_kernel<<<dim3(m.Vc, 8), 64, 0, s>>>(m, (const double2*)Dc64, (double2*)Ahat64);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

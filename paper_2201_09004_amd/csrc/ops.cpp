@@ -611,20 +611,21 @@ int tm_schur(OpEnv& e, int prec, Vec& out_e, const Vec& in_e, Vec& tmp_o, int re
 }
 
 int tm_schur_source(OpEnv& e, Vec& bhat_e, const Vec& b) {
-  int r = ensure_links(e, 64);
-  if (!r) r = ensure_clover(e, 64);
+  const int prec = b.prec;
+  int r = ensure_links(e, prec);
+  if (!r) r = ensure_clover(e, prec);
   if (r) return r;
   const Clover* c = get_clover(e);
   const Geom& g = e.f->g;
-  Vec t_o = make_vec(g, 64, 12, b.ncol, 1, 1, e.s);
-  Vec u_e = make_vec(g, 64, 12, b.ncol, 1, 0, e.s);
+  Vec t_o = make_vec(g, prec, 12, b.ncol, 1, 1, e.s);
+  Vec u_e = make_vec(g, prec, 12, b.ncol, 1, 0, e.s);
   if (!t_o.ok() || !u_e.ok()) return fail(LQ_ENOMEM, "schur source buffers");
-  if (launch_site(g, 64, c->H[0], c->Ainv[0], e.act.mu, true, b.f, t_o.f, 1, b.ncol, e.s))
+  if (launch_site(g, prec, c->H[pidx(prec)], c->Ainv[pidx(prec)], e.act.mu, true, b.f, t_o.f, 1, b.ncol, e.s))
     return fail(LQ_EDEVICE, "site");
   WilsonArgs A{};
-  A.prec = 64;
+  A.prec = prec;
   A.ncol = b.ncol;
-  A.links = links_for(e, 64);
+  A.links = links_for(e, prec);
   A.in = t_o.f;
   A.out = u_e.f;
   A.x = b.f;
@@ -634,23 +635,24 @@ int tm_schur_source(OpEnv& e, Vec& bhat_e, const Vec& b) {
   A.epi = EPI_XPAY;
   r = run_wilson(e, A, 3, 0, 48);
   if (r) return r;
-  if (launch_site(g, 64, c->H[0], c->Ainv[0], e.act.mu, true, u_e.f, bhat_e.f, 0, b.ncol, e.s))
+  if (launch_site(g, prec, c->H[pidx(prec)], c->Ainv[pidx(prec)], e.act.mu, true, u_e.f, bhat_e.f, 0, b.ncol, e.s))
     return fail(LQ_EDEVICE, "site");
   return 0;
 }
 
 int tm_schur_reconstruct(OpEnv& e, Vec& x, const Vec& x_e, const Vec& b) {
-  int r = ensure_links(e, 64);
-  if (!r) r = ensure_clover(e, 64);
+  const int prec = x.prec;
+  int r = ensure_links(e, prec);
+  if (!r) r = ensure_clover(e, prec);
   if (r) return r;
   const Clover* c = get_clover(e);
   const Geom& g = e.f->g;
-  Vec u_o = make_vec(g, 64, 12, b.ncol, 1, 1, e.s);
+  Vec u_o = make_vec(g, prec, 12, b.ncol, 1, 1, e.s);
   if (!u_o.ok()) return fail(LQ_ENOMEM, "reconstruct buffers");
   WilsonArgs A{};
-  A.prec = 64;
+  A.prec = prec;
   A.ncol = b.ncol;
-  A.links = links_for(e, 64);
+  A.links = links_for(e, prec);
   // x_e into the even half of x (hop scaled by zero)
   A.in = x_e.f;
   A.out = x.f;
@@ -668,7 +670,7 @@ int tm_schur_reconstruct(OpEnv& e, Vec& x, const Vec& x_e, const Vec& b) {
   A.par_out = 1;
   r = run_wilson(e, A, 3, 0, 48);
   if (r) return r;
-  if (launch_site(g, 64, c->H[0], c->Ainv[0], e.act.mu, true, u_o.f, x.f, 1, b.ncol, e.s))
+  if (launch_site(g, prec, c->H[pidx(prec)], c->Ainv[pidx(prec)], e.act.mu, true, u_o.f, x.f, 1, b.ncol, e.s))
     return fail(LQ_EDEVICE, "site");
   return 0;
 }

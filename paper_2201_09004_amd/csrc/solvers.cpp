@@ -616,19 +616,115 @@ int gcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int p
   return rs;
 }
 
+// Flexible GCR with sloppy inner vectors: every cycle of kmax directions runs
+// in precision plo (directions z_k = K(r), w_k = M z_k, their Gram-Schmidt,
+// the iterated residual and the cycle's correction), and ends with an FP64
+// update: x += correction, then r = b - M x in FP64 starts the next cycle (a
+// reliable update per cycle).  *steps counts the directions.
+int fgcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, const PrecFn& K, int plo, Vec& x,
+               Vec& b, const std::vector<double>& tol, int maxiter, Counters& cnt, int kmax, const char* tag,
+               int* steps) {
+  const int n = b.ncol, nc = b.nc, npar = b.npar, par0 = b.par0;
+  hipStream_t s = bl.s;
+  Vec r = make_vec(g, 64, nc, n, npar, par0, s), q = make_vec(g, 64, nc, n, npar, par0, s);
+  Vec rs = make_vec(g, plo, nc, n, npar, par0, s), xs = make_vec(g, plo, nc, n, npar, par0, s);
+  std::vector<Vec> Z, W;
+  for (int k = 0; k < kmax; ++k) {
+    Z.push_back(make_vec(g, plo, nc, n, npar, par0, s));
+    W.push_back(make_vec(g, plo, nc, n, npar, par0, s));
+    if (!Z.back().ok() || !W.back().ok()) return fail(LQ_ENOMEM, "gcr buffers");
+  }
+  State st(n, s);
+  if (!r.ok() || !q.ok() || !rs.ok() || !xs.ok() || !st.ok()) return fail(LQ_ENOMEM, "gcr buffers");
+  for (int c = 0; c < n; ++c) {
+    for (int k = 0; k < ST_STRIDE; ++k) st.h(c, k) = 0.0;
+    st.h(c, ST_ACTIVE) = 1.0;
+  }
+  int e = st.push();
+  if (e) return e;
+  std::vector<double> bb, rr;
+  if ((e = col_norms(bl, b, bb))) return e;
+  auto converged = [&]() -> bool {
+    for (int c = 0; c < n; ++c)
+      if (bb[c] > 0 && rr[c] > tol[c] * tol[c] * bb[c]) return false;
+    return true;
+  };
+  auto to_aux = [&]() -> int {
+    return launch_scalar(SC_DOT_TO_AUX, bl.partial, bl.gridx, n, st.d(), s) ? fail(LQ_EDEVICE, "scalar") : 0;
+  };
+  auto true_res = [&]() -> int {
+    int rc = M_hi(q, x);
+    if (!rc) rc = bl.op(OP_XMY_NORM, &b, &q);
+    if (rc) return rc;
+    std::swap(r, q);
+    return col_norms(bl, r, rr);
+  };
+  int it = 0;
+  if ((e = true_res())) return e;
+  while (it < maxiter && !converged()) {
+    if ((e = vec_copy(rs, r)) || (e = vec_zero(xs))) return e;
+    for (int k = 0; k < kmax && it < maxiter; ++k) {
+      Vec& zk = Z[k];
+      Vec& wk = W[k];
+      if ((e = K(zk, rs, cnt)) || (e = M_lo(wk, zk))) return e;
+      for (int j = 0; j < k; ++j) {
+        if ((e = bl.op(OP_DOT, &W[j], &wk)) || (e = to_aux())) return e;
+        if ((e = bl.op(OP_AXMY, &W[j], &wk, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)) ||
+            (e = bl.op(OP_AXMY, &Z[j], &zk, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)))
+          return e;
+      }
+      std::vector<double> ww;
+      if ((e = col_norms(bl, wk, ww)) || (e = st.pull())) return e;
+      for (int c = 0; c < n; ++c) {
+        const double inv = ww[c] > 0 ? 1.0 / std::sqrt(ww[c]) : 0.0;
+        if (!std::isfinite(inv)) return fail(LQ_ENUMERIC, "GCR: non-finite direction norm");
+        st.h(c, ST_AUX) = inv;
+        st.h(c, ST_AUX + 1) = 0.0;
+      }
+      if ((e = st.push())) return e;
+      if ((e = bl.op(OP_SCALE, &wk, nullptr, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)) ||
+          (e = bl.op(OP_SCALE, &zk, nullptr, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)))
+        return e;
+      if ((e = bl.op(OP_DOT, &wk, &rs)) || (e = to_aux())) return e;
+      if ((e = bl.op(OP_AXPY, &zk, &xs, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)) ||
+          (e = bl.op(OP_AXMY, &wk, &rs, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)) ||
+          (e = col_norms(bl, rs, rr)))
+        return e;
+      ++it;
+      if (verbose()) {
+        double wr = 0.0;
+        for (int c = 0; c < n; ++c) wr = std::max(wr, bb[c] > 0 ? std::sqrt(rr[c] / bb[c]) : 0.0);
+        fprintf(stderr, "[lq] %s step %d: worst iterated rel. residual %.3e\n", tag, it, wr);
+      }
+      if (converged()) break;
+    }
+    // the cycle's correction in FP64, then the true residual
+    if (launch_axpy_mixed(x.f, 64, xs.f, plo, nc, n, npar, g.Vh, s)) return fail(LQ_EDEVICE, "axpy");
+    ++cnt.reliable;
+    if ((e = true_res())) return e;
+  }
+  if (steps) *steps = it;
+  return converged() ? LQ_OK : LQ_ENOCONV;
+}
+
 // One two-level V-cycle in FP32 as the preconditioner of the outer GCR on the
 // full-lattice D (sec. 2.1, Table 2's multigrid): restrict the residual, solve
-// the coarse system D_c e_c = R r by BiCGStab (FP32 coarse operator, FP64
-// reliable updates, to coarse_tol), prolong, then nu_post minimal-residual
-// steps on the fine level: r' = r - D e, then nu_post times
-// e += omega r', r' -= omega D r' with omega = <D r', r'> / |D r'|^2 per column.
+// the even-odd preconditioned coarse system by BiCGStab (FP32 coarse operator,
+// FP64 reliable updates, to coarse_tol), reconstruct and prolong, then smooth
+// on the fine level: with r' = r - D e, nu_post minimal-residual steps on the
+// even-odd system M_hat e_e = bhat_e(r') (t = residual, u = M_hat t with
+// <u, t> and |u|^2 fused into the stencil, e_e += omega t, t -= omega u,
+// omega = <u, t> / |u|^2 per column), then e += the reconstructed correction.
 struct MgCycle {
   OpEnv& env;
   const MgHier& h;
   Blas& bl;  // fine-level reductions (full lattice)
   int n;
-  Vec r32, e32, t32, u32, bc, xc;
-  Blas blc;
+  Vec r32, e32, t32, u32, bc, xc, be, xe, to, ue, tmp64, tmp32;
+  Vec she, sre, sue, sto, sde;  // smoother: even correction, residual, M_hat residual; odd temporary; full correction
+  Blas blc, ble;
+  DBuf red;
+  int tiles = 0;
   State st;
   Counters coarse;
   int cycles = 0;
@@ -640,9 +736,24 @@ struct MgCycle {
     e32 = make_vec(g, 32, 12, n, 2, 0, s);
     t32 = make_vec(g, 32, 12, n, 2, 0, s);
     u32 = make_vec(g, 32, 12, n, 2, 0, s);
-    bc = make_vec(h.gc, 64, 12, n, 1, 0, s);
-    xc = make_vec(h.gc, 64, 12, n, 1, 0, s);
-    if (!r32.ok() || !e32.ok() || !t32.ok() || !u32.ok() || !bc.ok() || !xc.ok() || !st.ok())
+    bc = make_vec(h.gc, 64, 12, n, 2, 0, s);
+    xc = make_vec(h.gc, 64, 12, n, 2, 0, s);
+    be = make_vec(h.gc, 64, 12, n, 1, 0, s);
+    xe = make_vec(h.gc, 64, 12, n, 1, 0, s);
+    ue = make_vec(h.gc, 64, 12, n, 1, 0, s);
+    to = make_vec(h.gc, 64, 12, n, 1, 1, s);
+    tmp64 = make_vec(h.gc, 64, 12, n, 1, 1, s);
+    tmp32 = make_vec(h.gc, 32, 12, n, 1, 1, s);
+    she = make_vec(g, 32, 12, n, 1, 0, s);
+    sre = make_vec(g, 32, 12, n, 1, 0, s);
+    sue = make_vec(g, 32, 12, n, 1, 0, s);
+    sto = make_vec(g, 32, 12, n, 1, 1, s);
+    sde = make_vec(g, 32, 12, n, 2, 0, s);
+    tiles = (g.Vh + 63) / 64;
+    red = DBuf(sizeof(double) * 4 * (size_t)tiles * n, s);
+    if (!r32.ok() || !e32.ok() || !t32.ok() || !u32.ok() || !bc.ok() || !xc.ok() || !be.ok() || !xe.ok() ||
+        !ue.ok() || !to.ok() || !tmp64.ok() || !tmp32.ok() || !she.ok() || !sre.ok() || !sue.ok() || !sto.ok() ||
+        !sde.ok() || !red.p || !st.ok())
       return fail(LQ_ENOMEM, "multigrid cycle buffers");
     for (int c = 0; c < n; ++c) {
       for (int k = 0; k < ST_STRIDE; ++k) st.h(c, k) = 0.0;
@@ -650,28 +761,42 @@ struct MgCycle {
     }
     int e = st.push();
     if (!e) e = blas_prepare(env.ctx, blc, h.gc, 1, n, s);
+    if (!e) e = blas_prepare(env.ctx, ble, g, 1, n, s);
     return e;
   }
+  // z = K r; r and z in FP32 are used in place, FP64 ones are converted
   int operator()(Vec& z, Vec& r) {
     int e = 0;
-    if ((e = vec_copy(r32, r)) || (e = mg_restrict(env, h, r32, bc)) || (e = vec_zero(xc))) return e;
-    OpFn C64 = [&](Vec& o, const Vec& i) { return mg_coarse_op(env, h, o, i); };
+    if (r.prec != 32 && (e = vec_copy(r32, r))) return e;
+    Vec& rin = r.prec == 32 ? r : r32;
+    Vec& ev = z.prec == 32 ? z : e32;
+    // coarse solve on the even aggregates: (1 - A_ee^-1 D_eo A_oo^-1 D_oe) x_e = bhat_e
+    if ((e = mg_restrict(env, h, rin, bc)) || (e = mg_schur_source(env, h, be, to, ue, bc)) || (e = vec_zero(xe)))
+      return e;
+    OpFn S = [&](Vec& o, const Vec& i) {
+      Vec t = view(i.prec == 64 ? tmp64 : tmp32, 0, i.ncol);
+      return mg_schur_op(env, h, o, i, t);
+    };
     std::vector<double> tolc(n, h.coarse_tol);
-    const int rc = bicgstab_mixed(blc, h.gc, C64, C64, 32, xc, bc, tolc, h.coarse_maxiter, 0.1, coarse, nullptr);
+    const int rc = bicgstab_mixed(blc, h.gc, S, S, 32, xe, be, tolc, h.coarse_maxiter, 0.1, coarse, nullptr);
     if (rc != LQ_OK && rc != LQ_ENOCONV) return rc;
-    if ((e = mg_prolong(env, h, xc, e32))) return e;
-    // fine-level smoothing on the residual of the coarse correction
-    if ((e = wilson_D(env, 32, t32, e32, false)) || (e = bl.op(OP_XMY_NORM, &r32, &t32))) return e;
+    if ((e = mg_schur_reconstruct(env, h, xc, xe, to))) return e;
+    if ((e = mg_prolong(env, h, xc, ev))) return e;
+    // fine-level smoothing on the residual of the coarse correction, on the even-odd system
+    if ((e = wilson_D(env, 32, t32, ev, false)) || (e = bl.op(OP_XMY_NORM, &rin, &t32))) return e;
+    if ((e = tm_schur_source(env, sre, t32)) || (e = vec_zero(she))) return e;
     for (int k = 0; k < h.nu_post; ++k) {
-      if ((e = wilson_D(env, 32, u32, t32, false)) || (e = bl.op(OP_DOT_NORM, &u32, &t32))) return e;
-      if (launch_scalar(SC_BICG_OMEGA, bl.partial, bl.gridx, n, st.d(), env.s)) return fail(LQ_EDEVICE, "scalar");
-      if ((e = bl.op(OP_AXPY, &t32, &e32, nullptr, nullptr, nullptr, st.d(), ST_OMEGA, ST_OMEGA))) return e;
+      if ((e = tm_schur(env, 32, sue, sre, sto, 2, red.as<double>()))) return e;
+      if (launch_scalar(SC_BICG_OMEGA, red.as<double>(), tiles, n, st.d(), env.s)) return fail(LQ_EDEVICE, "scalar");
+      if ((e = ble.op(OP_AXPY, &sre, &she, nullptr, nullptr, nullptr, st.d(), ST_OMEGA, ST_OMEGA))) return e;
       if (k + 1 < h.nu_post &&
-          (e = bl.op(OP_AXMY, &u32, &t32, nullptr, nullptr, nullptr, st.d(), ST_OMEGA, ST_OMEGA)))
+          (e = ble.op(OP_AXMY, &sue, &sre, nullptr, nullptr, nullptr, st.d(), ST_OMEGA, ST_OMEGA)))
         return e;
     }
+    if ((e = tm_schur_reconstruct(env, sde, she, t32)) || (e = bl.opi(OP_AXPY, &sde, &ev, nullptr, 1.0)))
+      return e;
     ++cycles;
-    return vec_copy(z, e32);
+    return z.prec == 32 ? 0 : vec_copy(z, e32);
   }
 };
 
@@ -1115,10 +1240,11 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
       MgCycle K(env, *h, bl, n_rhs);
       if ((e = K.init())) return e;
       PrecFn P = [&](Vec& z, Vec& r, Counters&) { return K(z, r); };
+      OpFn D32 = [&](Vec& o, const Vec& i) { return wilson_D(env, 32, o, i, false); };
       std::vector<double> tol_v(n_rhs, 0.5 * tol);
       for (int pass = 0; pass < 4; ++pass) {
         int steps = 0;
-        const int rs = fgcr(bl, g, D64, P, x, b, tol_v, maxiter, cnt, h->gcr_kmax, "mg-gcr", &steps);
+        const int rs = fgcr_mixed(bl, g, D64, D32, P, 32, x, b, tol_v, maxiter, cnt, h->gcr_kmax, "mg-gcr", &steps);
         if (rs != LQ_OK && rs != LQ_ENOCONV) return rs;
         cnt.iters += steps;
         if ((e = rel_residual(bl, D64, x, b, res, g))) return e;
@@ -1768,7 +1894,7 @@ int mg_setup(lq_ctx* c, const lq_action* act, lq_field* f, const lq_mg_params* m
   h->coarse_tol = mp->coarse_tol > 0 ? mp->coarse_tol : 0.1;
   h->coarse_maxiter = mp->coarse_maxiter > 0 ? mp->coarse_maxiter : 100;
   h->nu_post = mp->nu_post > 0 ? mp->nu_post : 4;
-  h->gcr_kmax = mp->gcr_kmax > 0 ? mp->gcr_kmax : 16;
+  h->gcr_kmax = mp->gcr_kmax > 0 ? mp->gcr_kmax : 8;
   if ((e = mg_init_maps(*h, g, mp->block, nv)) || (e = mg_build(env, *h, w))) {
     mg_release(h);
     return e;

@@ -59,9 +59,13 @@ def test_transfers_and_coarse_operator_match_oracle(ctx, Lx, block, nv):
             errs = (rel(got_r, want_r), rel(got_p, want_p), rel(got_c, want_c))
             print(prec, "restrict / prolong / coarse:", errs)
             assert max(errs) < bar, (prec, errs)
-            # column by column too (the kernels take the columns in groups of four)
+            # column by column too (the kernels take the columns in groups)
             for k in range(5):
                 assert rel(got_c[k], want_c[k]) < bar
+            # three columns take the narrow (vector-unit) coarse kernel, five the wide one
+            # (matrix cores in FP32)
+            got3 = L.lq_mg_apply(ctx, act, f, L.LQ_MG_COARSE, prec, vc[:3], (3,) + cshape[1:])
+            assert rel(got3, want_c[:3]) < bar
     finally:
         L.lq_field_free(f)
 
