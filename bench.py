@@ -123,7 +123,7 @@ def family_roofline(kernels, families):
 KERNEL_SOURCES = ["paper_2201_09004_amd/csrc/lq_common.h", "paper_2201_09004_amd/csrc/lq_kernels.h",
                   "paper_2201_09004_amd/csrc/wilson_impl.h", "paper_2201_09004_amd/csrc/wilson32.hip",
                   "paper_2201_09004_amd/csrc/wilson16.hip", "paper_2201_09004_amd/csrc/wilson.hip",
-                  "paper_2201_09004_amd/csrc/staggered.hip"]
+                  "paper_2201_09004_amd/csrc/staggered.hip", "paper_2201_09004_amd/csrc/blas.hip"]
 
 
 def kernel_sources_sha():
@@ -536,6 +536,7 @@ def bench_hisq(args, L, torch):
     # one of the vector kernels
     roof = family_roofline(kernels, names + vec_names)
     roof["share_of_step"] = round(kernels[roof["kernel"]]["total_ms"] / (ms_step * args.steps), 4)
+    roof["traffic"] = measured_traffic(roof["kernel"], "hisq_multishift_cg_32x32x32x96_12rhs_8mass")
     step_ms = ms_step * args.steps
     shares = {"stencils": round(sum(kernels[k]["total_ms"] for k in names if k in kernels) / step_ms, 3),
               "vector_kernels": round(kernels["blas"]["total_ms"] / step_ms, 3) if "blas" in kernels else None}

@@ -101,7 +101,6 @@ template <> struct HalfIO<32> {
   }
 };
 
-constexpr int MG_CB = 4;  // columns per thread in the transfer and coarse kernels
 
 __device__ __forceinline__ void fine_site(const MgGeom& m, int yb, int& cb, int& par) {
   const int v = m.fine[yb];
@@ -111,20 +110,21 @@ __device__ __forceinline__ void fine_site(const MgGeom& m, int yb, int& cb, int&
 
 // ---------------------------------------------------------------- transfers
 // restriction: coarse(col, Y, s nv + j) = sum over the aggregate's sites of
-// q_{Y,s,j}^dag v_s; one thread per (Y, s, j), MG_CB columns per thread
-template <int PF, int PC>
+// q_{Y,s,j}^dag v_s; one thread per (Y, s, j), CB columns per thread (the
+// basis is read once per CB columns)
+template <int PF, int PC, int CB>
 __global__ void __launch_bounds__(64) mg_restrict_kernel(MgGeom m, const void* Qv, FieldRef fine, FieldRef coarse,
                                                           int ncol) {
   using R = typename CxT<PF>::R;
   const int Y = blockIdx.x, t = threadIdx.x, n2 = 2 * m.nv;
   if (t >= n2) return;
   const int s = t / m.nv, j = t - s * m.nv;
-  const int col0 = blockIdx.y * MG_CB;
-  const int nc = min(MG_CB, ncol - col0);
+  const int col0 = blockIdx.y * CB;
+  const int nc = min(CB, ncol - col0);
   const cx<R>* Q = (const cx<R>*)Qv;
-  cx<R> acc[MG_CB];
+  cx<R> acc[CB];
 #pragma unroll
-  for (int c = 0; c < MG_CB; ++c) acc[c] = {0, 0};
+  for (int c = 0; c < CB; ++c) acc[c] = {0, 0};
   for (int b = 0; b < m.B; ++b) {
     const int yb = Y * m.B + b;
     int cb, par;
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(64) mg_restrict_kernel(MgGeom m, const void* Q
 #pragma unroll
     for (int c = 0; c < 6; ++c) qv[c] = q[c];
 #pragma unroll
-    for (int cc = 0; cc < MG_CB; ++cc) {
+    for (int cc = 0; cc < CB; ++cc) {
       if (cc < nc) {
         cx<R> v[6];
         HalfIO<PF>::ld(fine, (int64_t)(col0 + cc) * 2 + par, cb, s, v);
@@ -145,13 +145,13 @@ __global__ void __launch_bounds__(64) mg_restrict_kernel(MgGeom m, const void* Q
   }
   using RC = typename CxT<PC>::R;
 #pragma unroll
-  for (int cc = 0; cc < MG_CB; ++cc)
+  for (int cc = 0; cc < CB; ++cc)
     if (cc < nc) cst<PC>(coarse, m, col0 + cc, Y, t, cx<RC>{(RC)acc[cc].re, (RC)acc[cc].im});
 }
 
 // prolongation: fine(col, y)_s = sum_j coarse(col, Y(y), s nv + j) q_{Y,s,j}(y);
-// one thread per (aggregate site, chirality)
-template <int PC, int PF>
+// one thread per (aggregate site, chirality), CB columns per thread
+template <int PC, int PF, int CB>
 __global__ void __launch_bounds__(256) mg_prolong_kernel(MgGeom m, FieldRef coarse, const void* Qv, FieldRef fine,
                                                           int ncol) {
   using R = typename CxT<PF>::R;
@@ -159,12 +159,12 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(MgGeom m, FieldRef coar
   if (gid >= (int64_t)m.Vc * m.B * 2) return;
   const int yb = (int)(gid >> 1), s = (int)(gid & 1);
   const int Y = yb / m.B;
-  const int col0 = blockIdx.y * MG_CB;
-  const int nc = min(MG_CB, ncol - col0);
+  const int col0 = blockIdx.y * CB;
+  const int nc = min(CB, ncol - col0);
   const cx<R>* q = (const cx<R>*)Qv + (int64_t)yb * 2 * m.nv * 6 + (int64_t)s * m.nv * 6;
-  cx<R> acc[MG_CB][6];
+  cx<R> acc[CB][6];
 #pragma unroll
-  for (int cc = 0; cc < MG_CB; ++cc)
+  for (int cc = 0; cc < CB; ++cc)
 #pragma unroll
     for (int c = 0; c < 6; ++c) acc[cc][c] = {0, 0};
   for (int j = 0; j < m.nv; ++j) {
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(MgGeom m, FieldRef coar
 #pragma unroll
     for (int c = 0; c < 6; ++c) qv[c] = q[j * 6 + c];
 #pragma unroll
-    for (int cc = 0; cc < MG_CB; ++cc) {
+    for (int cc = 0; cc < CB; ++cc) {
       if (cc < nc) {
         const auto a = cld<PC>(coarse, m, col0 + cc, Y, s * m.nv + j);
         const cx<R> ar = {(R)a.re, (R)a.im};
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(MgGeom m, FieldRef coar
   int cb, par;
   fine_site(m, yb, cb, par);
 #pragma unroll
-  for (int cc = 0; cc < MG_CB; ++cc)
+  for (int cc = 0; cc < CB; ++cc)
     if (cc < nc) HalfIO<PF>::st(fine, (int64_t)(col0 + cc) * 2 + par, cb, s, acc[cc]);
 }
 
@@ -240,84 +240,80 @@ __global__ void __launch_bounds__(64) mg_stencil_kernel(MgGeom m, const void* Mv
   }
 }
 
-// The same stencil in FP32 on the matrix cores, 12 columns per wave: per
-// direction the complex product Y = M X (n2 x n2 times n2 x 12) is the real
-// product [Mr | Mi] [[Xr, Xi], [-Xi, Xr]] = [Yr | Yi], done as
-// v_mfma_f32_16x16x4f32 steps: rows of M in 16-row tiles, the 24 real output
-// columns in two 16-column tiles (8 padding columns), k in groups of 4; the
-// real and imaginary parts of one loaded matrix element feed the Mr and the Mi
-// step of the same k.  Lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and
-// D[4 (l / 16) + i][l % 16], i = 0..3.
+// The same stencil in FP32 on the matrix cores, 12 columns per workgroup:
+// per direction the complex product Y = M X (n2 x n2 times n2 x 12) is the
+// real product [Mr | Mi] [[Xr, Xi], [-Xi, Xr]] = [Yr | Yi], done as
+// v_mfma_f32_16x16x4f32 steps.  One wave per 16-row tile of M (n2 / 16
+// waves, the last tile padded), the 24 real output columns in two 16-column
+// tiles (8 padding columns), k in groups of 4; the real and imaginary parts
+// of one loaded matrix element feed the Mr and the Mi step of the same k.  A
+// wave issues all its matrix loads of a direction before its first MFMA.
+// Lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and D[4 (l / 16) + i][l % 16].
 typedef float mg_f4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(64) mg_stencil_mfma_kernel(MgGeom m, const void* Mv, int d0, int nd, FieldRef in,
-                                                              FieldRef out, FieldRef x, double a, double sgn,
-                                                              int par_out, int ncol) {
+__global__ void __launch_bounds__(256) mg_stencil_mfma_kernel(MgGeom m, const void* Mv, int d0, int nd, FieldRef in,
+                                                               FieldRef out, FieldRef x, double a, double sgn,
+                                                               int par_out, int ncol) {
   __shared__ float2 sx[64 * 12];
   __shared__ float so[2][64][13];
   const int Y = par_out == 2 ? blockIdx.x : m.csite[par_out * (m.Vc / 2) + blockIdx.x];
-  const int lane = threadIdx.x, r16 = lane & 15, q = lane >> 4, n2 = 2 * m.nv;
-  const int mtiles = (n2 + 15) >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r16 = lane & 15, q = lane >> 4;
+  const int n2 = 2 * m.nv, nkg = n2 >> 2;  // n2 <= 60: at most 15 k-groups
   const int col0 = blockIdx.y * 12;
   const int nc = min(12, ncol - col0);
-  mg_f4 acc[4][2];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t][0] = acc[t][1] = mg_f4{0.f, 0.f, 0.f, 0.f};
+  const int row = 16 * wv + r16;
+  mg_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
   for (int d = d0; d < d0 + nd; ++d) {
     const int Yn = d == 0 ? Y : m.nbr[Y * 8 + d - 1];
+    // this wave's matrix elements of the direction: A[row][4 kg + q], kg < nkg
+    const float2* M = (const float2*)Mv + ((int64_t)Y * 9 + d) * n2 * n2 + row;
+    float2 av[15];
+#pragma unroll
+    for (int kg = 0; kg < 15; ++kg)
+      av[kg] = (kg < nkg && row < n2) ? M[(int64_t)(4 * kg + q) * n2] : make_float2(0.f, 0.f);
     __syncthreads();
-    for (int e = lane; e < n2 * 12; e += 64) {
+    for (int e = tid; e < n2 * 12; e += blockDim.x) {
       const int k = e / 12, cc = e - k * 12;
       const cx<float> v = cc < nc ? cld<32>(in, m, col0 + cc, Yn, k) : cx<float>{0.f, 0.f};
       sx[e] = make_float2(v.re, v.im);
     }
     __syncthreads();
-    const float2* M = (const float2*)Mv + ((int64_t)Y * 9 + d) * n2 * n2;
-    for (int kg = 0; kg < (n2 >> 2); ++kg) {
-      const int k = 4 * kg + q;
-      float bR[2], bI[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int n = 16 * t + r16;
-        const float2 xv = n < 24 ? sx[k * 12 + (n < 12 ? n : n - 12)] : make_float2(0.f, 0.f);
-        bR[t] = n < 12 ? xv.x : (n < 24 ? xv.y : 0.f);
-        bI[t] = n < 12 ? -xv.y : (n < 24 ? xv.x : 0.f);
-      }
+    for (int kg = 0; kg < 15; ++kg) {
+      if (kg < nkg) {
+        const int k = 4 * kg + q;
+        float bR[2], bI[2];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (t < mtiles) {
-          const int row = 16 * t + r16;
-          const float2 av = row < n2 ? M[(int64_t)k * n2 + row] : make_float2(0.f, 0.f);
-          acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bR[0], acc[t][0], 0, 0, 0);
-          acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bI[0], acc[t][0], 0, 0, 0);
-          acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bR[1], acc[t][1], 0, 0, 0);
-          acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bI[1], acc[t][1], 0, 0, 0);
+        for (int t = 0; t < 2; ++t) {
+          const int n = 16 * t + r16;
+          const float2 xv = n < 24 ? sx[k * 12 + (n < 12 ? n : n - 12)] : make_float2(0.f, 0.f);
+          bR[t] = n < 12 ? xv.x : (n < 24 ? xv.y : 0.f);
+          bI[t] = n < 12 ? -xv.y : (n < 24 ? xv.x : 0.f);
         }
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kg].x, bR[0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kg].x, bR[1], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kg].y, bI[0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kg].y, bI[1], acc1, 0, 0, 0);
       }
     }
   }
   // D tiles -> [re / im][row][column] in LDS, then one complex output per (row, column)
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    if (t < mtiles) {
+  for (int u = 0; u < 2; ++u) {
+    const int n = 16 * u + r16;
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int n = 16 * u + r16;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = 16 * t + 4 * q + i;
-          if (n < 24 && row < 64) so[n < 12 ? 0 : 1][row][n < 12 ? n : n - 12] = acc[t][u][i];
-        }
-      }
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * wv + 4 * q + i;
+      const float v = u == 0 ? acc0[i] : acc1[i];
+      if (n < 24 && r < 64) so[n < 12 ? 0 : 1][r][n < 12 ? n : n - 12] = v;
     }
   }
   __syncthreads();
-  if (lane < n2) {
-    for (int cc = 0; cc < nc; ++cc) {
-      cx<float> o = {(float)sgn * so[0][lane][cc], (float)sgn * so[1][lane][cc]};
-      if (a != 0.0) o = o + (float)a * cld<32>(x, m, col0 + cc, Y, lane);
-      cst<32>(out, m, col0 + cc, Y, lane, o);
-    }
+  for (int e = tid; e < n2 * nc; e += blockDim.x) {
+    const int r = e / nc, cc = e - r * nc;
+    cx<float> o = {(float)sgn * so[0][r][cc], (float)sgn * so[1][r][cc]};
+    if (a != 0.0) o = o + (float)a * cld<32>(x, m, col0 + cc, Y, r);
+    cst<32>(out, m, col0 + cc, Y, r, o);
   }
 }
 
@@ -593,26 +589,42 @@ int launch_mg_restrict(const MgGeom& m, int pf, const void* Q, FieldRef fine, in
                        hipStream_t s) {
   if (ncol <= 0) return 0;
   if (2 * m.nv > 64) return -1;
-  dim3 grid(m.Vc, (ncol + MG_CB - 1) / MG_CB), block(64);
-  if (pf == 64 && pc == 64) mg_restrict_kernel<64, 64><<<grid, block, 0, s>>>(m, Q, fine, coarse, ncol);
-  else if (pf == 32 && pc == 64) mg_restrict_kernel<32, 64><<<grid, block, 0, s>>>(m, Q, fine, coarse, ncol);
-  else if (pf == 32 && pc == 32) mg_restrict_kernel<32, 32><<<grid, block, 0, s>>>(m, Q, fine, coarse, ncol);
-  else if (pf == 64 && pc == 32) mg_restrict_kernel<64, 32><<<grid, block, 0, s>>>(m, Q, fine, coarse, ncol);
-  else return -1;
-  return hipGetLastError() == hipSuccess ? 0 : -2;
+  const bool wide = ncol > 4;
+  dim3 grid(m.Vc, wide ? (ncol + 11) / 12 : (ncol + 3) / 4), block(64);
+#define LQ_MG_R(PF, PC)                                                                              \
+  if (pf == PF && pc == PC) {                                                                        \
+    if (wide) mg_restrict_kernel<PF, PC, 12><<<grid, block, 0, s>>>(m, Q, fine, coarse, ncol);       \
+    else mg_restrict_kernel<PF, PC, 4><<<grid, block, 0, s>>>(m, Q, fine, coarse, ncol);             \
+    return hipGetLastError() == hipSuccess ? 0 : -2;                                                 \
+  }
+  LQ_MG_R(64, 64)
+  LQ_MG_R(32, 64)
+  LQ_MG_R(32, 32)
+  LQ_MG_R(64, 32)
+#undef LQ_MG_R
+  return -1;
 }
 
 int launch_mg_prolong(const MgGeom& m, int pc, FieldRef coarse, int pf, const void* Q, FieldRef fine, int ncol,
                       hipStream_t s) {
   if (ncol <= 0) return 0;
   const int64_t n = (int64_t)m.Vc * m.B * 2;
-  dim3 grid((unsigned)((n + 255) / 256), (ncol + MG_CB - 1) / MG_CB), block(256);
-  if (pc == 64 && pf == 64) mg_prolong_kernel<64, 64><<<grid, block, 0, s>>>(m, coarse, Q, fine, ncol);
-  else if (pc == 64 && pf == 32) mg_prolong_kernel<64, 32><<<grid, block, 0, s>>>(m, coarse, Q, fine, ncol);
-  else if (pc == 32 && pf == 32) mg_prolong_kernel<32, 32><<<grid, block, 0, s>>>(m, coarse, Q, fine, ncol);
-  else if (pc == 32 && pf == 64) mg_prolong_kernel<32, 64><<<grid, block, 0, s>>>(m, coarse, Q, fine, ncol);
-  else return -1;
-  return hipGetLastError() == hipSuccess ? 0 : -2;
+  // twelve columns per thread for FP32 fine vectors (the V-cycle); four for FP64 (setup probes), whose
+  // twelve-column version needs all 256 registers
+  const bool wide = ncol > 4 && pf == 32;
+  dim3 grid((unsigned)((n + 255) / 256), wide ? (ncol + 11) / 12 : (ncol + 3) / 4), block(256);
+#define LQ_MG_P(PC, PF)                                                                              \
+  if (pc == PC && pf == PF) {                                                                        \
+    if (wide) mg_prolong_kernel<PC, PF, 12><<<grid, block, 0, s>>>(m, coarse, Q, fine, ncol);        \
+    else mg_prolong_kernel<PC, PF, 4><<<grid, block, 0, s>>>(m, coarse, Q, fine, ncol);              \
+    return hipGetLastError() == hipSuccess ? 0 : -2;                                                 \
+  }
+  LQ_MG_P(64, 64)
+  LQ_MG_P(64, 32)
+  LQ_MG_P(32, 32)
+  LQ_MG_P(32, 64)
+#undef LQ_MG_P
+  return -1;
 }
 
 int launch_mg_stencil(const MgGeom& m, int p, const void* M, int d0, int nd, FieldRef in, FieldRef out, FieldRef x,
@@ -624,7 +636,8 @@ int launch_mg_stencil(const MgGeom& m, int p, const void* M, int d0, int nd, Fie
   if (p == 64 && wide) mg_stencil_kernel<64, 12><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
   else if (p == 64) mg_stencil_kernel<64, 4><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
   else if (p == 32 && wide && mg_use_mfma())
-    mg_stencil_mfma_kernel<<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
+    mg_stencil_mfma_kernel<<<grid, dim3(64 * ((2 * m.nv + 15) / 16)), 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out,
+                                                                           ncol);
   else if (p == 32 && wide) mg_stencil_kernel<32, 12><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
   else if (p == 32) mg_stencil_kernel<32, 4><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
   else return -1;
