@@ -284,7 +284,8 @@ typedef struct {
 } lq_mg_params;
 
 /* Computes and stores the hierarchy.  stats: iters = setup BiCGStab iterations,
- * seconds = setup time.  LQ_EINVAL: action other than Wilson / twisted clover,
+ * seconds = setup time.  A setup replaces the field's previous hierarchy: it must
+ * not run while a solve with solver = 3 on the same field is in progress.  LQ_EINVAL: action other than Wilson / twisted clover,
  * block or n_vec out of range; LQ_ENUMERIC: a vector vanishes on an aggregate. */
 lq_status lq_mg_setup(lq_ctx *ctx, const lq_action *act, const lq_field *g, const lq_mg_params *mp,
                       lq_stats *stats);

@@ -720,7 +720,7 @@ struct MgCycle {
   const MgHier& h;
   Blas& bl;  // fine-level reductions (full lattice)
   int n;
-  Vec r32, e32, t32, u32, bc, xc, be, xe, to, ue, tmp64, tmp32;
+  Vec r32, e32, t32, bc, xc, be, xe, to, ue, tmp64, tmp32;
   Vec she, sre, sue, sto, sde;  // smoother: even correction, residual, M_hat residual; odd temporary; full correction
   Blas blc, ble;
   DBuf red;
@@ -728,14 +728,16 @@ struct MgCycle {
   State st;
   Counters coarse;
   int cycles = 0;
+  bool fp64_io = false;
   MgCycle(OpEnv& en, const MgHier& hh, Blas& b, int ncol) : env(en), h(hh), bl(b), n(ncol), st(ncol, en.s) {}
   int init() {
     const Geom& g = env.f->g;
     hipStream_t s = env.s;
-    r32 = make_vec(g, 32, 12, n, 2, 0, s);
-    e32 = make_vec(g, 32, 12, n, 2, 0, s);
+    if (fp64_io) {  // conversion buffers for callers passing FP64 residuals and directions
+      r32 = make_vec(g, 32, 12, n, 2, 0, s);
+      e32 = make_vec(g, 32, 12, n, 2, 0, s);
+    }
     t32 = make_vec(g, 32, 12, n, 2, 0, s);
-    u32 = make_vec(g, 32, 12, n, 2, 0, s);
     bc = make_vec(h.gc, 64, 12, n, 2, 0, s);
     xc = make_vec(h.gc, 64, 12, n, 2, 0, s);
     be = make_vec(h.gc, 64, 12, n, 1, 0, s);
@@ -751,7 +753,7 @@ struct MgCycle {
     sde = make_vec(g, 32, 12, n, 2, 0, s);
     tiles = (g.Vh + 63) / 64;
     red = DBuf(sizeof(double) * 4 * (size_t)tiles * n, s);
-    if (!r32.ok() || !e32.ok() || !t32.ok() || !u32.ok() || !bc.ok() || !xc.ok() || !be.ok() || !xe.ok() ||
+    if ((fp64_io && (!r32.ok() || !e32.ok())) || !t32.ok() || !bc.ok() || !xc.ok() || !be.ok() || !xe.ok() ||
         !ue.ok() || !to.ok() || !tmp64.ok() || !tmp32.ok() || !she.ok() || !sre.ok() || !sue.ok() || !sto.ok() ||
         !sde.ok() || !red.p || !st.ok())
       return fail(LQ_ENOMEM, "multigrid cycle buffers");
@@ -767,6 +769,7 @@ struct MgCycle {
   // z = K r; r and z in FP32 are used in place, FP64 ones are converted
   int operator()(Vec& z, Vec& r) {
     int e = 0;
+    if ((r.prec != 32 || z.prec != 32) && !fp64_io) return fail(LQ_EINVAL, "multigrid cycle: FP32 vectors expected");
     if (r.prec != 32 && (e = vec_copy(r32, r))) return e;
     Vec& rin = r.prec == 32 ? r : r32;
     Vec& ev = z.prec == 32 ? z : e32;
