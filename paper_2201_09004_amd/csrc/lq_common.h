@@ -280,32 +280,37 @@ template <> struct IO<16, 12> {
   }
 };
 
+// FP16 staggered sites are packed with their norm in one 16-byte chunk
+// (3 half2 + the FP32 norm), so a neighbour gather is one load
 template <> struct IO<16, 3> {
   using R = float;
   template <bool NT = false>
   static __device__ __forceinline__ void load(const FieldRef& f, int64_t blk, int cb, cx<R>* v) {
-    const unsigned* p = (const unsigned*)f.data;
-    const float n = ldx<NT>(f.norm + blk * f.Vh + cb);
+    const uint4 d = ldx<NT>((const uint4*)f.data + tix(blk, 0, 1, cb, f.Vh));
+    const float n = __uint_as_float(d.w);
+    const unsigned w[3] = {d.x, d.y, d.z};
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      unsigned w = ldx<NT>(p + tix(blk, c, 3, cb, f.Vh));
-      v[c] = {n * h2f((unsigned short)(w & 0xffffu)), n * h2f((unsigned short)(w >> 16))};
-    }
+    for (int c = 0; c < 3; ++c)
+      v[c] = {n * h2f((unsigned short)(w[c] & 0xffffu)), n * h2f((unsigned short)(w[c] >> 16))};
   }
   template <bool NT = false>
   static __device__ __forceinline__ void store(const FieldRef& f, int64_t blk, int cb, const cx<R>* v) {
-    unsigned* p = (unsigned*)f.data;
     const float n = fp16_site_norm(site_maxabs<3>(v));
     const float s = n > 0.f ? 1.0f / n : 0.f;
-    stx<NT>(f.norm + blk * f.Vh + cb, n);
+    unsigned w[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      stx<NT>(p + tix(blk, c, 3, cb, f.Vh), (unsigned)f2h(s * v[c].re) | ((unsigned)f2h(s * v[c].im) << 16));
+    for (int c = 0; c < 3; ++c) w[c] = (unsigned)f2h(s * v[c].re) | ((unsigned)f2h(s * v[c].im) << 16);
+    stx<NT>((uint4*)f.data + tix(blk, 0, 1, cb, f.Vh), make_uint4(w[0], w[1], w[2], __float_as_uint(n)));
   }
 };
 
-// Bytes of one site of one block (without FP16 norms) and of the norm.
-__host__ __device__ inline int site_bytes(int prec, int nc) { return prec == 64 ? nc * 16 : prec == 32 ? nc * 8 : nc * 4; }
+// Bytes of one site of one block in the main array (FP16 Wilson-type sites
+// keep their norm in a separate array, FP16 staggered sites hold it inline),
+// and whether the precision and shape keep a separate norm array.
+__host__ __device__ inline int site_bytes(int prec, int nc) {
+  return prec == 64 ? nc * 16 : prec == 32 ? nc * 8 : (nc == 3 ? 16 : nc * 4);
+}
+__host__ __device__ inline bool sep_norm(int prec, int nc) { return prec == 16 && nc != 3; }
 
 // ---------------------------------------------------------------- links
 // Link fields: T2 elements in groups (parity, mu) of NE elements per site

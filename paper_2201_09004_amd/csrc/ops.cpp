@@ -83,7 +83,7 @@ struct BlasProf {
   Prof all, one;
   char name[48];
   static double bytes(const BlasArgs& A) {
-    return (double)A.ncol * A.npar * A.Vh * blas_transfers(A.op) * (site_bytes(A.prec, A.nc) + (A.prec == 16 ? 4 : 0));
+    return (double)A.ncol * A.npar * A.Vh * blas_transfers(A.op) * (site_bytes(A.prec, A.nc) + (sep_norm(A.prec, A.nc) ? 4 : 0));
   }
   BlasProf(lq_ctx* c, const BlasArgs& A, hipStream_t s)
       : all(c, "blas", s, bytes(A)), one(c, (snprintf(name, sizeof(name), "blas%d_%s", A.prec, blas_name(A.op)), name),
@@ -103,7 +103,7 @@ Vec make_vec(const Geom& g, int prec, int nc, int ncol, int npar, int par0, hipS
   v.s = s;
   const size_t nblk = (size_t)ncol * npar;
   const size_t main = nblk * block_bytes(prec, nc, g.Vh);
-  const size_t nb = prec == 16 ? nblk * g.Vh * sizeof(float) : 0;
+  const size_t nb = sep_norm(prec, nc) ? nblk * g.Vh * sizeof(float) : 0;
   const size_t mainr = (main + 255) / 256 * 256;
   v.bytes = mainr + nb;
   v.f.npar = npar;
@@ -115,14 +115,14 @@ Vec make_vec(const Geom& g, int prec, int nc, int ncol, int npar, int par0, hipS
     return v;
   }
   v.f.data = p;
-  v.f.norm = prec == 16 ? (float*)((char*)p + mainr) : nullptr;
+  v.f.norm = sep_norm(prec, nc) ? (float*)((char*)p + mainr) : nullptr;
   return v;
 }
 
 size_t vec_bytes(const Geom& g, int prec, int nc, int ncol, int npar) {
   const size_t nblk = (size_t)ncol * npar;
   const size_t main = nblk * block_bytes(prec, nc, g.Vh);
-  const size_t nb = prec == 16 ? nblk * g.Vh * sizeof(float) : 0;
+  const size_t nb = sep_norm(prec, nc) ? nblk * g.Vh * sizeof(float) : 0;
   return (main + 255) / 256 * 256 + nb;
 }
 
@@ -141,7 +141,7 @@ Vec vec_at(const Geom& g, int prec, int nc, int ncol, int npar, int par0, void* 
   if (ncol == 0) return v;
   const size_t main = (size_t)ncol * npar * block_bytes(prec, nc, g.Vh);
   v.f.data = base;
-  v.f.norm = prec == 16 ? (float*)((char*)base + (main + 255) / 256 * 256) : nullptr;
+  v.f.norm = sep_norm(prec, nc) ? (float*)((char*)base + (main + 255) / 256 * 256) : nullptr;
   return v;
 }
 

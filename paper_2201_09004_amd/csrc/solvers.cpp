@@ -47,7 +47,7 @@ struct MsProf {
   Prof all, one;
   char name[32];
   static double bytes(const MsArgs& M, bool p) {
-    const double sb = (double)site_bytes(M.prec, M.nc) + (M.prec == 16 ? 4 : 0);
+    const double sb = (double)site_bytes(M.prec, M.nc) + (sep_norm(M.prec, M.nc) ? 4 : 0);
     const double cols = p ? M.nrhs + 4.0 * M.nshift * M.nrhs : 3.0 * M.nrhs;
     return cols * M.npar * M.Vh * sb;
   }
