@@ -255,18 +255,21 @@ lq_status lq_cheb_coeffs(double a, double b, int N, double *c);
 
 /* ---- Multigrid (sec. 2.1, Table 2: the multigrid inverter and its reusable
  * subspace setup) ------------------------------------------------------------
- * Two-level aggregation multigrid for LQ_WILSON and LQ_TM_CLOVER.  The lattice
- * is cut into aggregates of block[0..3] sites (coarse lattice L / block, x
- * fastest).  n_vec near-null vectors are split by chirality on every aggregate
- * and orthonormalised there (Gram-Schmidt in vector order), which gives the
- * prolongator P; restriction is P^dag and the coarse operator is the Galerkin
- * product D_c = P^dag D P, a nearest-neighbour stencil of (2 n_vec)^2 blocks.
- * The setup is kept with the field (one hierarchy per field, replaced by the
- * next setup, freed with the field) and used by lq_solve with solver = 3:
- * flexible GCR(gcr_kmax) in FP64 on D x = b, each direction from one V-cycle
- * in FP32: restrict the residual, solve the coarse system by BiCGStab to
- * coarse_tol (at most coarse_maxiter iterations), prolong, then nu_post
- * minimal-residual steps on D.
+ * Two-level aggregation multigrid for LQ_TM_CLOVER (the Wilson operator is the
+ * case c_sw = mu = 0).  The lattice is cut into aggregates of block[0..3] sites
+ * (coarse lattice L / block, x fastest).  n_vec near-null vectors are split by
+ * chirality on every aggregate and orthonormalised there (Gram-Schmidt in vector
+ * order), which gives the prolongator P; restriction is P^dag and the coarse
+ * operator is the Galerkin product D_c = P^dag D P, a nearest-neighbour stencil
+ * of (2 n_vec)^2 blocks.  The setup is kept with the field (one hierarchy per
+ * field, replaced by the next setup, freed with the field) and used by lq_solve
+ * with solver = 3: flexible GCR(gcr_kmax) on D x = b, its cycles in FP32 closed
+ * by FP64 updates (lq_params.maxiter counts its steps, default 1000; three
+ * cycles that cut the worst residual by less than 10% end the solve with
+ * LQ_ENOCONV), each direction from one V-cycle in FP32: restrict the residual,
+ * solve the even-odd preconditioned coarse system by BiCGStab to coarse_tol (at
+ * most coarse_maxiter iterations), prolong, then nu_post minimal-residual steps
+ * on the even-odd preconditioned fine system.
  * Coarse vectors (lq_mg_apply): host [n_rhs][Vc][2][n_vec] complex, index 0 of
  * the chirality axis for gamma5 = +1 (spins 0, 1 of the chiral basis). */
 typedef struct {

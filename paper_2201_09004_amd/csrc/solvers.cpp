@@ -620,7 +620,9 @@ int gcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int p
 // in precision plo (directions z_k = K(r), w_k = M z_k, their Gram-Schmidt,
 // the iterated residual and the cycle's correction), and ends with an FP64
 // update: x += correction, then r = b - M x in FP64 starts the next cycle (a
-// reliable update per cycle).  *steps counts the directions.
+// reliable update per cycle).  *steps counts the directions.  Three cycles
+// in a row that reduce the worst true residual by less than 10% end the solve
+// (LQ_ENOCONV).
 int fgcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, const PrecFn& K, int plo, Vec& x,
                Vec& b, const std::vector<double>& tol, int maxiter, Counters& cnt, int kmax, const char* tag,
                int* steps) {
@@ -659,9 +661,15 @@ int fgcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, cons
     std::swap(r, q);
     return col_norms(bl, r, rr);
   };
-  int it = 0;
+  auto worst = [&]() -> double {
+    double w = 0.0;
+    for (int c = 0; c < n; ++c) w = std::max(w, bb[c] > 0 ? rr[c] / bb[c] : 0.0);
+    return w;
+  };
+  int it = 0, stalled = 0;
   if ((e = true_res())) return e;
   while (it < maxiter && !converged()) {
+    const double before = worst();
     if ((e = vec_copy(rs, r)) || (e = vec_zero(xs))) return e;
     for (int k = 0; k < kmax && it < maxiter; ++k) {
       Vec& zk = Z[k];
@@ -702,6 +710,9 @@ int fgcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, cons
     if (launch_axpy_mixed(x.f, 64, xs.f, plo, nc, n, npar, g.Vh, s)) return fail(LQ_EDEVICE, "axpy");
     ++cnt.reliable;
     if ((e = true_res())) return e;
+    // three cycles in a row that reduce the worst true residual by less than 10% end the solve
+    stalled = worst() > 0.81 * before ? stalled + 1 : 0;
+    if (stalled >= 3) break;
   }
   if (steps) *steps = it;
   return converged() ? LQ_OK : LQ_ENOCONV;
@@ -1240,6 +1251,7 @@ int solve(lq_ctx* c, const lq_action* act, lq_field* f, const lq_params* prm, in
       // flexible GCR on the full lattice, one multigrid V-cycle per direction
       MgHier* h = f->mg;
       if (!mg_matches(h, act)) return fail(LQ_EINVAL, "solver 3 needs lq_mg_setup for this action on this field");
+      if (prm->maxiter <= 0) maxiter = 1000;  // outer steps, each one V-cycle
       MgCycle K(env, *h, bl, n_rhs);
       if ((e = K.init())) return e;
       PrecFn P = [&](Vec& z, Vec& r, Counters&) { return K(z, r); };
