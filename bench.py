@@ -437,7 +437,7 @@ def bench_tm_mg(args, L, torch):
     act = L.action(L.LQ_TM_CLOVER, m=M, mu=MU, c_sw=CSW)
     block = tuple(int(v) for v in args.mg_block.split(","))
     mp = L.mg_params(block=block, n_vec=args.mg_nvec, coarse_tol=args.mg_coarse_tol, nu_post=args.mg_nu,
-                     setup_passes=args.mg_passes, seed=11)
+                     setup_passes=args.mg_passes, gcr_kmax=args.mg_kmax, seed=11)
     log("multigrid setup", block, args.mg_nvec)
     torch.cuda.synchronize()
     ts = time.perf_counter()
@@ -480,7 +480,7 @@ def bench_tm_mg(args, L, torch):
         "config": {"workload": "tm_clover_mg_gcr_24x24x24x64_12rhs", "lattice": list(TM_LAT), "n_rhs": n_rhs,
                    "m": M, "c_sw": CSW, "mu": MU, "sources": "point", "tol": 1e-10, "block": list(block),
                    "n_vec": args.mg_nvec, "coarse_tol": args.mg_coarse_tol, "nu_post": args.mg_nu,
-                   "setup_passes": args.mg_passes},
+                   "setup_passes": args.mg_passes, "gcr_kmax": args.mg_kmax},
         "setup_seconds": round(t_setup, 3), "setup_iters": setup["iters"],
         "roofline": roof, "cpu_baseline": None, "worst_true_rel_res": worst,
         "outer_iters": [s["iters"] for s in stats], "restarts": [s["reliable_updates"] for s in stats],
@@ -1033,10 +1033,11 @@ def main():
     ap.add_argument("--serve-capacity", type=float, default=0.0,
                     help="closed-loop capacity in requests/s from an earlier run (serve; 0: measure it)")
     ap.add_argument("--mg-block", default="4,4,4,4", help="multigrid aggregate extents x,y,z,t (tm_mg)")
-    ap.add_argument("--mg-nvec", type=int, default=24, help="multigrid near-null vectors (tm_mg)")
+    ap.add_argument("--mg-nvec", type=int, default=30, help="multigrid near-null vectors (tm_mg)")
     ap.add_argument("--mg-coarse-tol", type=float, default=0.1, help="coarse solve tolerance (tm_mg)")
     ap.add_argument("--mg-nu", type=int, default=4, help="post-smoothing steps (tm_mg)")
     ap.add_argument("--mg-passes", type=int, default=2, help="setup inverse-iteration passes (tm_mg)")
+    ap.add_argument("--mg-kmax", type=int, default=8, help="outer GCR restart length (tm_mg)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "

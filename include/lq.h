@@ -274,7 +274,7 @@ lq_status lq_cheb_coeffs(double a, double b, int N, double *c);
  * the chirality axis for gamma5 = +1 (spins 0, 1 of the chiral basis). */
 typedef struct {
   int32_t block[4];        /* aggregate extents (x, y, z, t): each >= 2; L / block even and >= 2 */
-  int32_t n_vec;           /* near-null vectors: 6, 12, 18, 24 or 30 (0: 24) */
+  int32_t n_vec;           /* near-null vectors: 6, 12, 18, 24 or 30 (0: 30) */
   int32_t setup_passes;    /* inverse-iteration passes from random vectors (0: 2) */
   int32_t setup_maxiter;   /* even-odd BiCGStab iterations per pass at most (0: 200) */
   int32_t coarse_maxiter;  /* V-cycle: coarse BiCGStab iterations at most (0: 100) */

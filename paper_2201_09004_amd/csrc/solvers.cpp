@@ -1875,7 +1875,7 @@ int mg_setup(lq_ctx* c, const lq_action* act, lq_field* f, const lq_mg_params* m
   if (f->type != 0) return fail(LQ_EINVAL, "multigrid needs a Wilson gauge field");
   if (act->kind != LQ_TM_CLOVER) return fail(LQ_EINVAL, "multigrid is implemented for the twisted-clover action");
   const Geom& g = f->g;
-  const int nv = mp->n_vec > 0 ? mp->n_vec : 24;
+  const int nv = mp->n_vec > 0 ? mp->n_vec : 30;
   if (nv % 6 != 0 || nv > 30) return fail(LQ_EINVAL, "n_vec must be 6, 12, 18, 24 or 30");
   for (int mu = 0; mu < 4; ++mu) {
     const int b = mp->block[mu];

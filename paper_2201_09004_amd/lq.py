@@ -304,7 +304,7 @@ def lq_eigs(ctx, act, field, which, nev, tol=1e-10, max_restarts=0, filter_degre
 LQ_MG_RESTRICT, LQ_MG_PROLONG, LQ_MG_COARSE = 0, 1, 2
 
 
-def mg_params(block=(4, 4, 4, 4), n_vec=24, setup_passes=0, setup_maxiter=0, setup_tol=0.0, coarse_tol=0.0,
+def mg_params(block=(4, 4, 4, 4), n_vec=30, setup_passes=0, setup_maxiter=0, setup_tol=0.0, coarse_tol=0.0,
               coarse_maxiter=0, nu_post=0, gcr_kmax=0, seed=1, null_vecs=None):
     p = lq_mg_params(n_vec=n_vec, setup_passes=setup_passes, setup_maxiter=setup_maxiter,
                      coarse_maxiter=coarse_maxiter, setup_tol=setup_tol, coarse_tol=coarse_tol, seed=seed,
