@@ -240,60 +240,89 @@ __global__ void __launch_bounds__(64) mg_stencil_kernel(MgGeom m, const void* Mv
   }
 }
 
-// The same stencil in FP32 on the matrix cores, 12 columns per workgroup:
-// per direction the complex product Y = M X (n2 x n2 times n2 x 12) is the
-// real product [Mr | Mi] [[Xr, Xi], [-Xi, Xr]] = [Yr | Yi], done as
-// v_mfma_f32_16x16x4f32 steps.  One wave per 16-row tile of M (n2 / 16
-// waves, the last tile padded), the 24 real output columns in two 16-column
-// tiles (8 padding columns), k in groups of 4; the real and imaginary parts
-// of one loaded matrix element feed the Mr and the Mi step of the same k.  A
-// wave issues all its matrix loads of a direction before its first MFMA.
-// Lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and D[4 (l / 16) + i][l % 16].
+// The same stencil on the matrix cores, 12 columns per workgroup: per
+// direction the complex product Y = M X (n2 x n2 times n2 x 12) is the real
+// product [Mr | Mi] [[Xr, Xi], [-Xi, Xr]] = [Yr | Yi], done as 16x16x4 MFMA
+// steps (v_mfma_f32_16x16x4f32, or v_mfma_f64_16x16x4f64 for the FP64
+// stencil).  One wave per 16-row tile of M (n2 / 16 waves, the last tile
+// padded), the 24 real output columns in two 16-column tiles (8 padding
+// columns), k in groups of 4; the real and imaginary parts of one loaded
+// matrix element feed the Mr and the Mi step of the same k.  A wave issues all
+// its matrix loads of a direction before its first MFMA.  Lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; of the output tile it holds
+// D[4 (l / 16) + i][l % 16], i = 0..3, in FP32, and D[4 i + l / 16][l % 16]
+// in FP64.
 typedef float mg_f4 __attribute__((ext_vector_type(4)));
+typedef double mg_d4 __attribute__((ext_vector_type(4)));
 
+template <int P> struct MfmaT;
+template <> struct MfmaT<32> {
+  using R = float;
+  using C2 = float2;
+  using V4 = mg_f4;
+  static __device__ __forceinline__ V4 mma(R a, R b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ __forceinline__ int drow(int q, int i) { return 4 * q + i; }
+};
+template <> struct MfmaT<64> {
+  using R = double;
+  using C2 = double2;
+  using V4 = mg_d4;
+  static __device__ __forceinline__ V4 mma(R a, R b, V4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ __forceinline__ int drow(int q, int i) { return 4 * i + q; }
+};
+
+template <int P>
 __global__ void __launch_bounds__(256) mg_stencil_mfma_kernel(MgGeom m, const void* Mv, int d0, int nd, FieldRef in,
                                                                FieldRef out, FieldRef x, double a, double sgn,
                                                                int par_out, int ncol) {
-  __shared__ float2 sx[64 * 12];
-  __shared__ float so[2][64][13];
+  using T = MfmaT<P>;
+  using R = typename T::R;
+  using C2 = typename T::C2;
+  __shared__ C2 sx[64 * 12];
+  __shared__ R so[2][64][13];
   const int Y = par_out == 2 ? blockIdx.x : m.csite[par_out * (m.Vc / 2) + blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r16 = lane & 15, q = lane >> 4;
   const int n2 = 2 * m.nv, nkg = n2 >> 2;  // n2 <= 60: at most 15 k-groups
   const int col0 = blockIdx.y * 12;
   const int nc = min(12, ncol - col0);
   const int row = 16 * wv + r16;
-  mg_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  typename T::V4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
   for (int d = d0; d < d0 + nd; ++d) {
     const int Yn = d == 0 ? Y : m.nbr[Y * 8 + d - 1];
     // this wave's matrix elements of the direction: A[row][4 kg + q], kg < nkg
-    const float2* M = (const float2*)Mv + ((int64_t)Y * 9 + d) * n2 * n2 + row;
-    float2 av[15];
+    const C2* M = (const C2*)Mv + ((int64_t)Y * 9 + d) * n2 * n2 + row;
+    C2 av[15];
 #pragma unroll
-    for (int kg = 0; kg < 15; ++kg)
-      av[kg] = (kg < nkg && row < n2) ? M[(int64_t)(4 * kg + q) * n2] : make_float2(0.f, 0.f);
+    for (int kg = 0; kg < 15; ++kg) {
+      if (kg < nkg && row < n2) av[kg] = M[(int64_t)(4 * kg + q) * n2];
+      else av[kg].x = av[kg].y = 0;
+    }
     __syncthreads();
     for (int e = tid; e < n2 * 12; e += blockDim.x) {
       const int k = e / 12, cc = e - k * 12;
-      const cx<float> v = cc < nc ? cld<32>(in, m, col0 + cc, Yn, k) : cx<float>{0.f, 0.f};
-      sx[e] = make_float2(v.re, v.im);
+      const cx<R> v = cc < nc ? cld<P>(in, m, col0 + cc, Yn, k) : cx<R>{0, 0};
+      sx[e].x = v.re;
+      sx[e].y = v.im;
     }
     __syncthreads();
 #pragma unroll
     for (int kg = 0; kg < 15; ++kg) {
       if (kg < nkg) {
         const int k = 4 * kg + q;
-        float bR[2], bI[2];
+        R bR[2], bI[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           const int n = 16 * t + r16;
-          const float2 xv = n < 24 ? sx[k * 12 + (n < 12 ? n : n - 12)] : make_float2(0.f, 0.f);
-          bR[t] = n < 12 ? xv.x : (n < 24 ? xv.y : 0.f);
-          bI[t] = n < 12 ? -xv.y : (n < 24 ? xv.x : 0.f);
+          C2 xv;
+          xv.x = xv.y = 0;
+          if (n < 24) xv = sx[k * 12 + (n < 12 ? n : n - 12)];
+          bR[t] = n < 12 ? xv.x : (n < 24 ? xv.y : (R)0);
+          bI[t] = n < 12 ? -xv.y : (n < 24 ? xv.x : (R)0);
         }
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kg].x, bR[0], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kg].x, bR[1], acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kg].y, bI[0], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kg].y, bI[1], acc1, 0, 0, 0);
+        acc0 = T::mma(av[kg].x, bR[0], acc0);
+        acc1 = T::mma(av[kg].x, bR[1], acc1);
+        acc0 = T::mma(av[kg].y, bI[0], acc0);
+        acc1 = T::mma(av[kg].y, bI[1], acc1);
       }
     }
   }
@@ -303,17 +332,17 @@ __global__ void __launch_bounds__(256) mg_stencil_mfma_kernel(MgGeom m, const vo
     const int n = 16 * u + r16;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int r = 16 * wv + 4 * q + i;
-      const float v = u == 0 ? acc0[i] : acc1[i];
+      const int r = 16 * wv + T::drow(q, i);
+      const R v = u == 0 ? acc0[i] : acc1[i];
       if (n < 24 && r < 64) so[n < 12 ? 0 : 1][r][n < 12 ? n : n - 12] = v;
     }
   }
   __syncthreads();
   for (int e = tid; e < n2 * nc; e += blockDim.x) {
     const int r = e / nc, cc = e - r * nc;
-    cx<float> o = {(float)sgn * so[0][r][cc], (float)sgn * so[1][r][cc]};
-    if (a != 0.0) o = o + (float)a * cld<32>(x, m, col0 + cc, Y, r);
-    cst<32>(out, m, col0 + cc, Y, r, o);
+    cx<R> o = {(R)sgn * so[0][r][cc], (R)sgn * so[1][r][cc]};
+    if (a != 0.0) o = o + (R)a * cld<P>(x, m, col0 + cc, Y, r);
+    cst<P>(out, m, col0 + cc, Y, r, o);
   }
 }
 
@@ -633,11 +662,14 @@ int launch_mg_stencil(const MgGeom& m, int p, const void* M, int d0, int nd, Fie
   if (2 * m.nv > 64 || d0 < 0 || nd < 0 || d0 + nd > 9 || par_out < 0 || par_out > 2) return -1;
   const bool wide = ncol > 4;
   dim3 grid(par_out == 2 ? m.Vc : m.Vc / 2, wide ? (ncol + 11) / 12 : 1), block(64);
-  if (p == 64 && wide) mg_stencil_kernel<64, 12><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
+  if (p == 64 && wide && mg_use_mfma())
+    mg_stencil_mfma_kernel<64><<<grid, dim3(64 * ((2 * m.nv + 15) / 16)), 0, s>>>(m, M, d0, nd, in, out, x, a, sgn,
+                                                                               par_out, ncol);
+  else if (p == 64 && wide) mg_stencil_kernel<64, 12><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
   else if (p == 64) mg_stencil_kernel<64, 4><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
   else if (p == 32 && wide && mg_use_mfma())
-    mg_stencil_mfma_kernel<<<grid, dim3(64 * ((2 * m.nv + 15) / 16)), 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out,
-                                                                           ncol);
+    mg_stencil_mfma_kernel<32><<<grid, dim3(64 * ((2 * m.nv + 15) / 16)), 0, s>>>(m, M, d0, nd, in, out, x, a, sgn,
+                                                                               par_out, ncol);
   else if (p == 32 && wide) mg_stencil_kernel<32, 12><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
   else if (p == 32) mg_stencil_kernel<32, 4><<<grid, block, 0, s>>>(m, M, d0, nd, in, out, x, a, sgn, par_out, ncol);
   else return -1;
