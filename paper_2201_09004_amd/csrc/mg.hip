@@ -25,6 +25,15 @@ namespace lq {
 
 namespace {
 
+typedef float mg_f4 __attribute__((ext_vector_type(4)));
+typedef double mg_d4 __attribute__((ext_vector_type(4)));
+
+// the coarse stencil and the prolongation on the matrix cores unless LQ_MG_VALU is set
+inline bool mg_use_mfma() {
+  static const bool v = getenv("LQ_MG_VALU") == nullptr;
+  return v;
+}
+
 template <int P> struct CxT;
 template <> struct CxT<64> { using T = double2; using R = double; };
 template <> struct CxT<32> { using T = float2; using R = float; };
@@ -188,6 +197,96 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(MgGeom m, FieldRef coar
     if (cc < nc) HalfIO<PF>::st(fine, (int64_t)(col0 + cc) * 2 + par, cb, s, acc[cc]);
 }
 
+// Prolongation into FP32 fine vectors on the matrix cores: for one
+// (aggregate, chirality) the fine block F (6 B rows (site, component) x 12
+// columns) is Q (6 B x nv) times the coarse block V (nv x 12), as the real
+// product [Qr | Qi] [[Vr, Vi], [-Vi, Vr]] = [Fr | Fi] with
+// v_mfma_f32_16x16x4f32: 16-row tiles of F, two 16-column tiles for the 24
+// real columns, k (the vector index) in groups of 4 padded to nv rounded up.
+// One workgroup of four waves per (aggregate, chirality), V staged in LDS; each
+// wave takes every fourth row tile and stages its output tile in LDS to write
+// complex pairs.  Lane layouts as in the coarse stencil.
+template <int PC>
+__global__ void __launch_bounds__(256) mg_prolong_mfma_kernel(MgGeom m, FieldRef coarse, const float2* Q,
+                                                               FieldRef fine, int ncol) {
+  __shared__ float2 sv[32 * 12];
+  __shared__ float so[4][16][25];
+  const int Y = blockIdx.x >> 1, s = blockIdx.x & 1;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r16 = lane & 15, q = lane >> 4;
+  const int col0 = blockIdx.y * 12;
+  const int nc = min(12, ncol - col0);
+  const int nv = m.nv, nkg = (nv + 3) >> 2;
+  for (int e = tid; e < 32 * 12; e += blockDim.x) {
+    const int j = e / 12, cc = e - j * 12;
+    float2 v = make_float2(0.f, 0.f);
+    if (j < nv && cc < nc) {
+      const auto a = cld<PC>(coarse, m, col0 + cc, Y, s * nv + j);
+      v = make_float2((float)a.re, (float)a.im);
+    }
+    sv[e] = v;
+  }
+  __syncthreads();
+  // B operands of this lane for each k-group (the same for every row tile)
+  float bR[8][2], bI[8][2];
+#pragma unroll
+  for (int kg = 0; kg < 8; ++kg) {
+    const int k = 4 * kg + q;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int n = 16 * t + r16;
+      const float2 xv = n < 24 ? sv[k * 12 + (n < 12 ? n : n - 12)] : make_float2(0.f, 0.f);
+      bR[kg][t] = n < 12 ? xv.x : (n < 24 ? xv.y : 0.f);
+      bI[kg][t] = n < 12 ? -xv.y : (n < 24 ? xv.x : 0.f);
+    }
+  }
+  const int rows = 6 * m.B, ntile = (rows + 15) >> 4;
+  const int64_t sstride = (int64_t)2 * nv * 6;  // complex entries between in-block sites
+  const float2* QY = Q + (int64_t)Y * m.B * sstride + (int64_t)s * nv * 6;
+  for (int tile = wv; tile < ntile; tile += 4) {
+    const int row = 16 * tile + r16;
+    const int b = row / 6, c = row - 6 * b;
+    mg_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kg = 0; kg < 8; ++kg) {
+      if (kg < nkg) {
+        const int j = 4 * kg + q;
+        const float2 av = (row < rows && j < nv) ? QY[(int64_t)b * sstride + j * 6 + c] : make_float2(0.f, 0.f);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bR[kg][0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bR[kg][1], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bI[kg][0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bI[kg][1], acc1, 0, 0, 0);
+      }
+    }
+    // the wave's output tile through LDS: so[wave][row in tile][real column]
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int n = 16 * u + r16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (n < 24) so[wv][4 * q + i][n] = u == 0 ? acc0[i] : acc1[i];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int e = lane; e < 16 * 12; e += 64) {
+      const int rr = e / 12, cc = e - rr * 12;
+      const int orow = 16 * tile + rr;
+      if (cc < nc && orow < rows) {
+        const int ob = orow / 6, oc = orow - 6 * ob;
+        int cb, par;
+        fine_site(m, Y * m.B + ob, cb, par);
+        const int comp = 6 * s + oc;
+        float2* p = (float2*)fine.data;
+        p[2 * tix((int64_t)(col0 + cc) * 2 + par, comp >> 1, 6, cb, fine.Vh) + (comp & 1)] =
+            make_float2(so[wv][rr][cc], so[wv][rr][12 + cc]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 // ---------------------------------------------------------------- coarse stencil
 // The generic coarse stencil over the aggregates Y of parity par_out (2: all):
 //   out(Y) = a x(Y) + sgn sum_{d = d0}^{d0 + nd - 1} M[Y][d] in(N_d(Y))
@@ -252,9 +351,6 @@ __global__ void __launch_bounds__(64) mg_stencil_kernel(MgGeom m, const void* Mv
 // A[l % 16][l / 16] and B[l / 16][l % 16]; of the output tile it holds
 // D[4 (l / 16) + i][l % 16], i = 0..3, in FP32, and D[4 i + l / 16][l % 16]
 // in FP64.
-typedef float mg_f4 __attribute__((ext_vector_type(4)));
-typedef double mg_d4 __attribute__((ext_vector_type(4)));
-
 template <int P> struct MfmaT;
 template <> struct MfmaT<32> {
   using R = float;
@@ -604,12 +700,6 @@ __global__ void __launch_bounds__(64) mg_site_mul_kernel(MgGeom m, const double2
   }
 }
 
-// the FP32 coarse stencil on the matrix cores unless LQ_MG_VALU is set
-inline bool mg_use_mfma() {
-  static const bool v = getenv("LQ_MG_VALU") == nullptr;
-  return v;
-}
-
 inline int grid_for(int64_t n, int bs) { return (int)std::min<int64_t>((n + bs - 1) / bs, 1 << 20); }
 
 }  // namespace
@@ -641,6 +731,12 @@ int launch_mg_prolong(const MgGeom& m, int pc, FieldRef coarse, int pf, const vo
   // twelve columns per thread for FP32 fine vectors (the V-cycle); four for FP64 (setup probes), whose
   // twelve-column version needs all 256 registers
   const bool wide = ncol > 4 && pf == 32;
+  if (wide && mg_use_mfma() && m.nv <= 32) {
+    dim3 g2(m.Vc * 2, (ncol + 11) / 12);
+    if (pc == 64) mg_prolong_mfma_kernel<64><<<g2, 256, 0, s>>>(m, coarse, (const float2*)Q, fine, ncol);
+    else mg_prolong_mfma_kernel<32><<<g2, 256, 0, s>>>(m, coarse, (const float2*)Q, fine, ncol);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+  }
   dim3 grid((unsigned)((n + 255) / 256), wide ? (ncol + 11) / 12 : (ncol + 3) / 4), block(256);
 #define LQ_MG_P(PC, PF)                                                                              \
   if (pc == PC && pf == PF) {                                                                        \
