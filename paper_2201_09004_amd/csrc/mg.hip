@@ -122,11 +122,13 @@ __device__ __forceinline__ void fine_site(const MgGeom& m, int yb, int& cb, int&
 // q_{Y,s,j}^dag v_s; one thread per (Y, s, j), CB columns per thread (the
 // basis is read once per CB columns)
 template <int PF, int PC, int CB>
-__global__ void __launch_bounds__(64) mg_restrict_kernel(MgGeom m, const void* Qv, FieldRef fine, FieldRef coarse,
-                                                          int ncol) {
+__global__ void __launch_bounds__(256) mg_restrict_kernel(MgGeom m, const void* Qv, FieldRef fine, FieldRef coarse,
+                                                           int ncol) {
   using R = typename CxT<PF>::R;
-  const int Y = blockIdx.x, t = threadIdx.x, n2 = 2 * m.nv;
-  if (t >= n2) return;
+  // four waves split the aggregate's sites, their sums meet in LDS
+  __shared__ cx<R> part[3][64][CB];
+  const int Y = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n2 = 2 * m.nv;
+  const int t = lane < n2 ? lane : n2 - 1;  // idle lanes repeat the last row and store nothing
   const int s = t / m.nv, j = t - s * m.nv;
   const int col0 = blockIdx.y * CB;
   const int nc = min(CB, ncol - col0);
@@ -134,7 +136,8 @@ __global__ void __launch_bounds__(64) mg_restrict_kernel(MgGeom m, const void* Q
   cx<R> acc[CB];
 #pragma unroll
   for (int c = 0; c < CB; ++c) acc[c] = {0, 0};
-  for (int b = 0; b < m.B; ++b) {
+  const int bq = (m.B + 3) >> 2, b0 = wv * bq, b1 = min(m.B, b0 + bq);
+  for (int b = b0; b < b1; ++b) {
     const int yb = Y * m.B + b;
     int cb, par;
     fine_site(m, yb, cb, par);
@@ -152,6 +155,15 @@ __global__ void __launch_bounds__(64) mg_restrict_kernel(MgGeom m, const void* Q
       }
     }
   }
+  if (wv > 0)
+#pragma unroll
+    for (int cc = 0; cc < CB; ++cc) part[wv - 1][lane][cc] = acc[cc];
+  __syncthreads();
+  if (wv > 0 || lane >= n2) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int cc = 0; cc < CB; ++cc) acc[cc] = acc[cc] + part[w][lane][cc];
   using RC = typename CxT<PC>::R;
 #pragma unroll
   for (int cc = 0; cc < CB; ++cc)
@@ -709,7 +721,7 @@ int launch_mg_restrict(const MgGeom& m, int pf, const void* Q, FieldRef fine, in
   if (ncol <= 0) return 0;
   if (2 * m.nv > 64) return -1;
   const bool wide = ncol > 4;
-  dim3 grid(m.Vc, wide ? (ncol + 11) / 12 : (ncol + 3) / 4), block(64);
+  dim3 grid(m.Vc, wide ? (ncol + 11) / 12 : (ncol + 3) / 4), block(256);
 #define LQ_MG_R(PF, PC)                                                                              \
   if (pf == PF && pc == PC) {                                                                        \
     if (wide) mg_restrict_kernel<PF, PC, 12><<<grid, block, 0, s>>>(m, Q, fine, coarse, ncol);       \
