@@ -465,7 +465,7 @@ def bench_tm_mg(args, L, torch):
     value = n_rhs * args.steps / (t1 - t0)
     worst = max(s["true_rel_res"] for s in stats)
     names = ([f"wilson{p}_{e}" for p in (32, 64) for e in ("site", "clovinv", "xmy", "xmyt", "xpay")] +
-             ["mg_restrict", "mg_prolong", "mg_coarse32", "mg_coarse64", "mg_hop32", "mg_hop64", "site"])
+             ["mg_restrict", "mg_prolong", "mg_coarse32", "mg_coarse64", "mg_hop32", "mg_hop64", "mg_cgs", "site"])
     vec_names = [f"blas{p}_{o}" for p in (32, 64) for o in BLAS_OPS]
     kernels = profile_table(L, ctx, names + vec_names + ["blas"])
     L.lq_profile(ctx, False)

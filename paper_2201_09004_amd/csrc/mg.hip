@@ -454,6 +454,103 @@ __global__ void __launch_bounds__(256) mg_stencil_mfma_kernel(MgGeom m, const vo
   }
 }
 
+// ---------------------------------------------------------------- block Gram-Schmidt
+// Classical Gram-Schmidt step of the outer flexible GCR on k <= 8 earlier
+// directions: c_j = <W_j, w> for all j in one pass over w (per-block partials,
+// summed in block order: deterministic), then w -= sum_j c_j W_j and
+// z -= sum_j c_j Z_j in one pass.
+struct MgVecSet {
+  FieldRef f[8];
+};
+
+template <int P>
+__global__ void __launch_bounds__(256) mg_mdot_kernel(MgVecSet W, int k, FieldRef w, int npar, double* partial) {
+  using R = typename CxT<P>::R;
+  __shared__ double sm[4][16];
+  const int col = blockIdx.y, ncol = gridDim.y;
+  const int64_t n = (int64_t)npar * w.Vh;
+  double acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int par = (int)(i / w.Vh), cb = (int)(i - (int64_t)par * w.Vh);
+    const int64_t blk = (int64_t)col * npar + par;
+    cx<R> b[12];
+    IO<P, 12>::load(w, blk, cb, b);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j < k) {
+        cx<R> a[12];
+        IO<P, 12>::load(W.f[j], blk, cb, a);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          acc[2 * j] += (double)a[c].re * (double)b[c].re + (double)a[c].im * (double)b[c].im;
+          acc[2 * j + 1] += (double)a[c].re * (double)b[c].im - (double)a[c].im * (double)b[c].re;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    for (int o = 32; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sm[wv][j] = acc[j];
+  __syncthreads();
+  if (threadIdx.x < 2 * k) {
+    const int j = threadIdx.x;
+    double v = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) v += sm[q][j];
+    partial[((int64_t)(j >> 1) * ncol + col) * gridDim.x * 2 + (int64_t)blockIdx.x * 2 + (j & 1)] = v;
+  }
+}
+
+__global__ void mg_mdot_sum_kernel(const double* partial, int k, int ncol, int gridx, double* coef) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= k * ncol) return;
+  const double* p = partial + (int64_t)t * gridx * 2;
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b < gridx; ++b) {
+    re += p[2 * b];
+    im += p[2 * b + 1];
+  }
+  coef[2 * t] = re;
+  coef[2 * t + 1] = im;
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) mg_maxmy_kernel(MgVecSet W, MgVecSet Z, int k, FieldRef w, FieldRef z,
+                                                        int npar, const double* coef) {
+  using R = typename CxT<P>::R;
+  const int col = blockIdx.y, ncol = gridDim.y;
+  const int64_t n = (int64_t)npar * w.Vh;
+  cx<R> c[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    c[j] = j < k ? cx<R>{(R)coef[2 * (j * ncol + col)], (R)coef[2 * (j * ncol + col) + 1]} : cx<R>{0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int par = (int)(i / w.Vh), cb = (int)(i - (int64_t)par * w.Vh);
+    const int64_t blk = (int64_t)col * npar + par;
+    cx<R> x[12], y[12], a[12];
+    IO<P, 12>::load(w, blk, cb, x);
+    IO<P, 12>::load(z, blk, cb, y);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j < k) {
+        IO<P, 12>::load(W.f[j], blk, cb, a);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) x[q] = x[q] - c[j] * a[q];
+        IO<P, 12>::load(Z.f[j], blk, cb, a);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) y[q] = y[q] - c[j] * a[q];
+      }
+    }
+    IO<P, 12>::store(w, blk, cb, x);
+    IO<P, 12>::store(z, blk, cb, y);
+  }
+}
+
 // ---------------------------------------------------------------- setup
 // Q[:, :, s, j, :] = chirality-s half of fine column j (FP64)
 __global__ void __launch_bounds__(256) mg_gather_kernel(MgGeom m, FieldRef fine, double2* Q) {
@@ -830,6 +927,24 @@ int launch_mg_random(FieldRef fine, int ncol, uint64_t seed, hipStream_t s) {
   const int64_t n = (int64_t)ncol * 2 * fine.Vh;
   if (n <= 0) return 0;
   mg_random_kernel<<<grid_for(n, 256), 256, 0, s>>>(fine, ncol, seed);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_mg_cgs(int prec, const FieldRef* W, const FieldRef* Z, int k, FieldRef w, FieldRef z, int ncol, int npar,
+                  int gridx, double* partial, double* coef, hipStream_t s) {
+  if (k <= 0 || ncol <= 0) return 0;
+  if (k > 8 || (prec != 32 && prec != 64)) return -1;
+  MgVecSet Ws{}, Zs{};
+  for (int j = 0; j < k; ++j) {
+    Ws.f[j] = W[j];
+    Zs.f[j] = Z[j];
+  }
+  dim3 grid(gridx, ncol);
+  if (prec == 32) mg_mdot_kernel<32><<<grid, 256, 0, s>>>(Ws, k, w, npar, partial);
+  else mg_mdot_kernel<64><<<grid, 256, 0, s>>>(Ws, k, w, npar, partial);
+  mg_mdot_sum_kernel<<<(k * ncol + 63) / 64, 64, 0, s>>>(partial, k, ncol, gridx, coef);
+  if (prec == 32) mg_maxmy_kernel<32><<<grid, 256, 0, s>>>(Ws, Zs, k, w, z, npar, coef);
+  else mg_maxmy_kernel<64><<<grid, 256, 0, s>>>(Ws, Zs, k, w, z, npar, coef);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -617,7 +617,8 @@ int gcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, int p
 }
 
 // Flexible GCR with sloppy inner vectors: every cycle of kmax directions runs
-// in precision plo (directions z_k = K(r), w_k = M z_k, their Gram-Schmidt,
+// in precision plo (directions z_k = K(r), w_k = M z_k, their classical
+// Gram-Schmidt against the earlier directions in one pass,
 // the iterated residual and the cycle's correction), and ends with an FP64
 // update: x += correction, then r = b - M x in FP64 starts the next cycle (a
 // reliable update per cycle).  *steps counts the directions.  Three cycles
@@ -637,7 +638,9 @@ int fgcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, cons
     if (!Z.back().ok() || !W.back().ok()) return fail(LQ_ENOMEM, "gcr buffers");
   }
   State st(n, s);
-  if (!r.ok() || !q.ok() || !rs.ok() || !xs.ok() || !st.ok()) return fail(LQ_ENOMEM, "gcr buffers");
+  DBuf cgs_part((size_t)8 * n * bl.gridx * 2 * sizeof(double), s), cgs_coef((size_t)8 * n * 2 * sizeof(double), s);
+  if (!r.ok() || !q.ok() || !rs.ok() || !xs.ok() || !st.ok() || !cgs_part.p || !cgs_coef.p)
+    return fail(LQ_ENOMEM, "gcr buffers");
   for (int c = 0; c < n; ++c) {
     for (int k = 0; k < ST_STRIDE; ++k) st.h(c, k) = 0.0;
     st.h(c, ST_ACTIVE) = 1.0;
@@ -675,11 +678,20 @@ int fgcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, cons
       Vec& zk = Z[k];
       Vec& wk = W[k];
       if ((e = K(zk, rs, cnt)) || (e = M_lo(wk, zk))) return e;
-      for (int j = 0; j < k; ++j) {
-        if ((e = bl.op(OP_DOT, &W[j], &wk)) || (e = to_aux())) return e;
-        if ((e = bl.op(OP_AXMY, &W[j], &wk, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)) ||
-            (e = bl.op(OP_AXMY, &Z[j], &zk, nullptr, nullptr, nullptr, st.d(), ST_AUX, ST_AUX)))
-          return e;
+      // classical Gram-Schmidt against the earlier directions, up to 8 in one pass
+      for (int j0 = 0; j0 < k; j0 += 8) {
+        FieldRef Wf[8], Zf[8];
+        const int kk = std::min(8, k - j0);
+        for (int j = 0; j < kk; ++j) {
+          Wf[j] = W[j0 + j].f;
+          Zf[j] = Z[j0 + j].f;
+        }
+        // algorithmic bytes: w and the W_j read for the dots, then W_j, Z_j read and w, z read and written
+        const double vb = (double)wk.bytes > 0 ? (double)wk.bytes : (double)vec_bytes(g, plo, nc, n, npar);
+        Prof pc(bl.ctx, "mg_cgs", s, vb * (3.0 * kk + 5.0));
+        if (launch_mg_cgs(plo, Wf, Zf, kk, wk.f, zk.f, n, npar, bl.gridx, cgs_part.as<double>(),
+                          cgs_coef.as<double>(), s))
+          return fail(LQ_EDEVICE, "gram-schmidt");
       }
       std::vector<double> ww;
       if ((e = col_norms(bl, wk, ww)) || (e = st.pull())) return e;
