@@ -363,6 +363,36 @@ def bench_tm(args, L, torch):
     roof["launches_at_full_width"] = kernels_w[dom]["count"]
     roof["copy_kernel_gbs"] = copy_peak(L, ctx)
 
+    mg = None
+    if not args.no_mg:
+        # the same propagator by the two-level multigrid GCR (NEXT-4 row), timed beside
+        # the bench line: setup once, one untimed solve, then the median of three
+        log("multigrid propagator")
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        L.lq_mg_setup(ctx, act, field, L.mg_params(block=(4, 4, 4, 4), n_vec=30, seed=11))
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - ts
+        pmg = L.params(tol=1e-10, solver=3, maxiter=300)
+        x_d.zero_()
+        L.lq_solve(ctx, act, field, pmg, b_d, x_d)
+        runs, its, worst_mg = [], [], 0.0
+        for _ in range(3):
+            x_d.zero_()
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, smg = L.lq_solve(ctx, act, field, pmg, b_d, x_d)
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - ta)
+            its.append(smg["iters"])
+            worst_mg = max(worst_mg, smg["true_rel_res"])
+        tmg = sorted(runs)[1]
+        mg = {"solves_per_s": round(n_rhs / tmg, 4), "seconds_median_of_3": round(tmg, 4),
+              "setup_seconds_incl_first_tuning": round(t_setup, 3), "outer_steps": its,
+              "worst_true_rel_res": worst_mg, "speedup_vs_bicgstab": round((n_rhs / tmg) / value, 3),
+              "config": "4^4 aggregates, 30 vectors, FP32 V-cycles, flexible GCR(8)"}
+        log("multigrid", mg)
+
     fp64 = None
     if not args.no_fp64:
         # the plain FP64 solver on one column: one untimed solve (it also tunes
@@ -413,6 +443,7 @@ def bench_tm(args, L, torch):
         "solve_stencil_gflops": round(sum(s["gflops"] for s in stats) / len(stats), 1),
         "fp64_single_column": fp64,
         "speedup_vs_fp64_single_column": (value / fp64["solves_per_s"]) if fp64 else None,
+        "multigrid": mg,
         "kernels": kernels,
     }
 
@@ -1027,6 +1058,7 @@ def main():
                                            "overlap_deflated", "serve", "wilson"), default="tm")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 single-column comparison")
+    ap.add_argument("--no-mg", action="store_true", help="skip the multigrid propagator beside the bench line (tm)")
     ap.add_argument("--recon12", type=int, default=0)
     ap.add_argument("--serve-requests", type=int, default=256, help="requests per arrival rate (serve)")
     ap.add_argument("--serve-rates", default="0.5,0.8,0.95", help="arrival rates as fractions of capacity (serve)")
