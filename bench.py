@@ -539,7 +539,7 @@ def bench_hisq(args, L, torch):
     del V_d, W_d
     torch.cuda.empty_cache()
     act = L.action(L.LQ_HISQ, m=HISQ_MASSES[0])
-    prm = L.params(tol=1e-10, sloppy_bits=16, masses=HISQ_MASSES)
+    prm = L.params(tol=1e-10, sloppy_bits=args.hisq_sloppy, masses=HISQ_MASSES)
     x_d = torch.zeros((len(HISQ_MASSES),) + tuple(b_d.shape), dtype=b_d.dtype, device=dev)
     for _ in range(args.warmup):
         _, st = L.lq_solve(ctx, act, field, prm, b_d, x_d)
@@ -584,7 +584,7 @@ def bench_hisq(args, L, torch):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "hisq_multishift_cg_32x32x32x96_12rhs_8mass", "lattice": list(HISQ_LAT),
                    "n_rhs": n_rhs, "masses": HISQ_MASSES,
-                   "sloppy": "fp32 multi-shift, fp16 refinement, fp64 reliable", "tol": 1e-10},
+                   "sloppy": f"fp32 multi-shift, fp{args.hisq_sloppy} refinement, fp64 reliable", "tol": 1e-10},
         "roofline": roof, "cpu_baseline": cpu, "worst_true_rel_res": worst,
         "time_shares": shares,
         "mass_columns_per_s": round(value * len(HISQ_MASSES), 3),
@@ -1059,6 +1059,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 single-column comparison")
     ap.add_argument("--no-mg", action="store_true", help="skip the multigrid propagator beside the bench line (tm)")
+    ap.add_argument("--hisq-sloppy", type=int, default=16, choices=(16, 32), help="refinement storage (hisq)")
     ap.add_argument("--recon12", type=int, default=0)
     ap.add_argument("--serve-requests", type=int, default=256, help="requests per arrival rate (serve)")
     ap.add_argument("--serve-rates", default="0.5,0.8,0.95", help="arrival rates as fractions of capacity (serve)")
