@@ -498,7 +498,7 @@ __global__ void __launch_bounds__(256) mg_mdot_kernel(MgVecSet W, int k, FieldRe
 #pragma unroll
     for (int j = 0; j < 16; ++j) sm[wv][j] = acc[j];
   __syncthreads();
-  if (threadIdx.x < 2 * k) {
+  if ((int)threadIdx.x < 2 * k) {
     const int j = threadIdx.x;
     double v = 0.0;
     for (int q = 0; q < (int)(blockDim.x >> 6); ++q) v += sm[q][j];
