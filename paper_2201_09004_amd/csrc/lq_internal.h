@@ -291,6 +291,9 @@ int mg_apply_host(lq_ctx* c, const lq_action* act, lq_field* f, int op, int prec
                   double* out, hipStream_t s);
 int mg_setup(lq_ctx* c, const lq_action* act, lq_field* f, const lq_mg_params* mp, lq_stats* st, hipStream_t s);
 bool mg_matches(const MgHier* h, const lq_action* act);
+// the setup's probe vectors on the fine lattice (FP64, ncol <= 12 columns): basis vector
+// (k0 + kk) of the aggregates of coarse parity class cls in column kk, zero elsewhere (mg.hip)
+int launch_mg_probe_fine(const MgGeom& m, const void* Q64, FieldRef fine, int ncol, int k0, int cls, hipStream_t s);
 // one classical Gram-Schmidt step over k <= 8 directions (mg.hip): coef[j][col] = <W_j, w>,
 // then w -= sum_j coef_j W_j and z -= sum_j coef_j Z_j; partial holds k * ncol * gridx * 2 doubles
 int launch_mg_cgs(int prec, const FieldRef* W, const FieldRef* Z, int k, FieldRef w, FieldRef z, int ncol, int npar,

@@ -150,17 +150,14 @@ int mg_build(OpEnv& e, MgHier& h, Vec& vecs) {
   if (nbad) return fail(LQ_ENUMERIC, "multigrid: a near-null vector vanishes on an aggregate");
   // probing, 12 coarse components at a time
   const int nb = std::min(12, n2);
-  Vec pc = make_vec(h.gc, 64, 12, nb, 2, 0, s);
   Vec pf = make_vec(e.f->g, 64, 12, nb, 2, 0, s);
   Vec df = make_vec(e.f->g, 64, 12, nb, 2, 0, s);
-  if (!pc.ok() || !pf.ok() || !df.ok()) return fail(LQ_ENOMEM, "multigrid probes");
+  if (!pf.ok() || !df.ok()) return fail(LQ_ENOMEM, "multigrid probes");
   for (int cls = 0; cls < 16; ++cls)
     for (int k0 = 0; k0 < n2; k0 += nb) {
       const int w = std::min(nb, n2 - k0);
-      Vec pcw = view(pc, 0, w), pfw = view(pf, 0, w), dfw = view(df, 0, w);
-      if (launch_mg_probe_source(m, pcw.f, w, k0, cls, s) ||
-          launch_mg_prolong(m, 64, pcw.f, 64, h.Q64, pfw.f, w, s))
-        return fail(LQ_EDEVICE, "multigrid probe");
+      Vec pfw = view(pf, 0, w), dfw = view(df, 0, w);
+      if (launch_mg_probe_fine(m, h.Q64, pfw.f, w, k0, cls, s)) return fail(LQ_EDEVICE, "multigrid probe");
       int r = wilson_D(e, 64, dfw, pfw, false);
       if (r) return r;
       if (launch_mg_probe_restrict(m, h.Q64, dfw.f, w, k0, cls, h.Dc64, s)) return fail(LQ_EDEVICE, "multigrid probe");

@@ -653,44 +653,92 @@ __global__ void __launch_bounds__(256) mg_probe_source_kernel(MgGeom m, FieldRef
 // hops of its two mu-neighbours, the one at Y - mu on its lower mu-face and
 // the one at Y + mu on its upper mu-face (blocks are at least 2 sites deep, so
 // the faces are disjoint).  Other aggregates receive nothing.
-__global__ void __launch_bounds__(64) mg_probe_restrict_kernel(MgGeom m, const double2* Q, FieldRef fine, int ncol,
-                                                                int k0, int cls, double2* Dc) {
-  const int Y = blockIdx.x, t = threadIdx.x, n2 = 2 * m.nv;
-  if (t >= n2) return;
-  const int s = t / m.nv, j = t - s * m.nv;
+__global__ void __launch_bounds__(256) mg_probe_restrict_kernel(MgGeom m, const double2* Q, FieldRef fine, int ncol,
+                                                                 int k0, int cls, double2* Dc) {
+  // four waves split the aggregate's sites; the ncol (<= 12) probe columns are
+  // taken together so that the basis is read once; partial sums meet in LDS
+  __shared__ double2 part[3][64][2][12];
+  const int Y = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n2 = 2 * m.nv;
   const int bits = m.cpar[Y] ^ cls;
-  int mu = -1;
-  if (bits != 0) {
-    if (bits & (bits - 1)) return;
-    mu = __ffs(bits) - 1;
-  }
-  for (int kk = 0; kk < ncol; ++kk) {
-    cx<double> lo = {0, 0}, hi = {0, 0};
-    for (int b = 0; b < m.B; ++b) {
-      const int yb = Y * m.B + b;
-      const int fb = m.face[yb];
-      const bool in_lo = mu < 0 || (fb >> (2 * mu)) & 1;
-      const bool in_hi = mu >= 0 && (fb >> (2 * mu + 1)) & 1;
-      if (!in_lo && !in_hi) continue;
-      int cb, par;
-      fine_site(m, yb, cb, par);
-      cx<double> v[6];
-      HalfIO<64>::ld(fine, (int64_t)kk * 2 + par, cb, s, v);
-      const double2* q = Q + (((int64_t)yb * 2 + s) * m.nv + j) * 6;
-      cx<double> acc = {0, 0};
+  if (bits & (bits - 1)) return;  // the whole workgroup: no aggregate of this class is next to Y
+  const int mu = bits ? __ffs(bits) - 1 : -1;
+  const int t = lane < n2 ? lane : n2 - 1;
+  const int s = t / m.nv, j = t - s * m.nv;
+  cx<double> lo[12], hi[12];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) fmac(acc, cx<double>{q[c].x, q[c].y}, v[c]);
-      if (in_lo) lo = lo + acc;
-      if (in_hi) hi = hi + acc;
+  for (int kk = 0; kk < 12; ++kk) lo[kk] = hi[kk] = cx<double>{0, 0};
+  const int bq = (m.B + 3) >> 2, b0 = wv * bq, b1 = min(m.B, b0 + bq);
+  for (int b = b0; b < b1; ++b) {
+    const int yb = Y * m.B + b;
+    const int fb = m.face[yb];
+    const bool in_lo = mu < 0 || (fb >> (2 * mu)) & 1;
+    const bool in_hi = mu >= 0 && (fb >> (2 * mu + 1)) & 1;
+    if (!in_lo && !in_hi) continue;
+    int cb, par;
+    fine_site(m, yb, cb, par);
+    const double2* q = Q + (((int64_t)yb * 2 + s) * m.nv + j) * 6;
+    cx<double> qv[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) qv[c] = cx<double>{q[c].x, q[c].y};
+#pragma unroll
+    for (int kk = 0; kk < 12; ++kk) {
+      if (kk < ncol) {
+        cx<double> v[6];
+        HalfIO<64>::ld(fine, (int64_t)kk * 2 + par, cb, s, v);
+        cx<double> acc = {0, 0};
+#pragma unroll
+        for (int c = 0; c < 6; ++c) fmac(acc, qv[c], v[c]);
+        if (in_lo) lo[kk] = lo[kk] + acc;
+        if (in_hi) hi[kk] = hi[kk] + acc;
+      }
     }
+  }
+  if (wv > 0)
+#pragma unroll
+    for (int kk = 0; kk < 12; ++kk) {
+      part[wv - 1][lane][0][kk] = make_double2(lo[kk].re, lo[kk].im);
+      part[wv - 1][lane][1][kk] = make_double2(hi[kk].re, hi[kk].im);
+    }
+  __syncthreads();
+  if (wv > 0 || lane >= n2) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int kk = 0; kk < 12; ++kk) {
+      lo[kk] = lo[kk] + cx<double>{part[w][lane][0][kk].x, part[w][lane][0][kk].y};
+      hi[kk] = hi[kk] + cx<double>{part[w][lane][1][kk].x, part[w][lane][1][kk].y};
+    }
+  for (int kk = 0; kk < ncol; ++kk) {
     const int k = k0 + kk;
     if (mu < 0) {
-      Dc[(((int64_t)Y * 9) * n2 + k) * n2 + t] = make_double2(lo.re, lo.im);
+      Dc[(((int64_t)Y * 9) * n2 + k) * n2 + t] = make_double2(lo[kk].re, lo[kk].im);
     } else {
-      Dc[(((int64_t)Y * 9 + 2 + 2 * mu) * n2 + k) * n2 + t] = make_double2(lo.re, lo.im);
-      Dc[(((int64_t)Y * 9 + 1 + 2 * mu) * n2 + k) * n2 + t] = make_double2(hi.re, hi.im);
+      Dc[(((int64_t)Y * 9 + 2 + 2 * mu) * n2 + k) * n2 + t] = make_double2(lo[kk].re, lo[kk].im);
+      Dc[(((int64_t)Y * 9 + 1 + 2 * mu) * n2 + k) * n2 + t] = make_double2(hi[kk].re, hi[kk].im);
     }
   }
+}
+
+// the probe fine vectors directly: column kk is chirality s = (k0 + kk) / nv of
+// basis vector j = (k0 + kk) % nv on the aggregates of class cls, zero elsewhere
+__global__ void __launch_bounds__(256) mg_probe_fine_kernel(MgGeom m, const double2* Q, FieldRef fine, int ncol,
+                                                             int k0, int cls) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)m.Vc * m.B * ncol) return;
+  const int yb = (int)(gid % ((int64_t)m.Vc * m.B)), kk = (int)(gid / ((int64_t)m.Vc * m.B));
+  const int Y = yb / m.B;
+  const int d = k0 + kk, s = d / m.nv, j = d - s * m.nv;
+  cx<double> v[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = cx<double>{0, 0};
+  if (m.cpar[Y] == cls) {
+    const double2* q = Q + (((int64_t)yb * 2 + s) * m.nv + j) * 6;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[6 * s + c] = cx<double>{q[c].x, q[c].y};
+  }
+  int cb, par;
+  fine_site(m, yb, cb, par);
+  IO<64, 12>::store(fine, (int64_t)kk * 2 + par, cb, v);
 }
 
 __global__ void __launch_bounds__(256) mg_narrow_kernel(const double2* src, float2* dst, int64_t n) {
@@ -912,8 +960,15 @@ int launch_mg_probe_source(const MgGeom& m, FieldRef coarse, int ncol, int k0, i
 int launch_mg_probe_restrict(const MgGeom& m, const void* Q64, FieldRef fine, int ncol, int k0, int cls, void* Dc64,
                              hipStream_t s) {
   if (ncol <= 0) return 0;
-  if (2 * m.nv > 64) return -1;
-  mg_probe_restrict_kernel<<<m.Vc, 64, 0, s>>>(m, (const double2*)Q64, fine, ncol, k0, cls, (double2*)Dc64);
+  if (2 * m.nv > 64 || ncol > 12) return -1;
+  mg_probe_restrict_kernel<<<m.Vc, 256, 0, s>>>(m, (const double2*)Q64, fine, ncol, k0, cls, (double2*)Dc64);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_mg_probe_fine(const MgGeom& m, const void* Q64, FieldRef fine, int ncol, int k0, int cls, hipStream_t s) {
+  const int64_t n = (int64_t)m.Vc * m.B * ncol;
+  if (n <= 0) return 0;
+  mg_probe_fine_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(m, (const double2*)Q64, fine, ncol, k0, cls);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
