@@ -327,7 +327,7 @@ def bench_tm(args, L, torch):
     field = L.lq_gauge_load(ctx, TM_LAT, U_d)
     del U_d
     act = L.action(L.LQ_TM_CLOVER, m=M, mu=MU, c_sw=CSW)
-    prm = L.params(tol=1e-10, sloppy_bits=32, recon12=args.recon12)
+    prm = L.params(tol=1e-10, sloppy_bits=32, recon12=args.recon12, reliable_delta=args.delta)
 
     log("warmup")
     for _ in range(args.warmup):
@@ -1061,6 +1061,7 @@ def main():
     ap.add_argument("--no-mg", action="store_true", help="skip the multigrid propagator beside the bench line (tm)")
     ap.add_argument("--hisq-sloppy", type=int, default=16, choices=(16, 32), help="refinement storage (hisq)")
     ap.add_argument("--recon12", type=int, default=0)
+    ap.add_argument("--delta", type=float, default=0.0, help="reliable-update threshold (tm; 0: the library default 0.1)")
     ap.add_argument("--serve-requests", type=int, default=256, help="requests per arrival rate (serve)")
     ap.add_argument("--serve-rates", default="0.5,0.8,0.95", help="arrival rates as fractions of capacity (serve)")
     ap.add_argument("--serve-capacity", type=float, default=0.0,
