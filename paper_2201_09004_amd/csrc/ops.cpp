@@ -509,7 +509,8 @@ static int run_wilson(OpEnv& e, WilsonArgs& A, int n_fields, int clov_mats, int 
   char key[160];
   snprintf(key, sizeof(key), "%s_r%d_d%d_n%d_v%d_p%d", name, A.recon, A.dag, col_bucket(A.ncol), A.g.Vh, A.par_out);
   const bool blocked = !A.dag && (A.epi == EPI_CLOVINV || A.epi == EPI_XMY_CLOVINV || A.epi == EPI_XPAY ||
-                                  A.epi == EPI_XPAY_G5 || A.epi == EPI_CHEB || A.epi == EPI_XMY_RTS);
+                                  A.epi == EPI_XPAY_G5 || A.epi == EPI_CHEB || A.epi == EPI_XMY_RTS ||
+                                  A.epi == EPI_SITE);
   const int out_npar = A.out.npar;
   // timed under the kernel's name and under name_n<columns> (solvers that drop
   // converged columns launch the same kernel at several widths)

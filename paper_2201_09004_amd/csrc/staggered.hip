@@ -40,8 +40,12 @@ __device__ __forceinline__ void stag_hop1(const StagArgs& A, const int c[4], int
   for (int r = 0; r < NR; ++r) IO<P, 3>::load(A.in, blk_index(A.in, min(col0 + r, A.ncol - 1), pin), nb, xn[r]);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    {
-      const cx<R>* x = xn[r];
+    const cx<R>* x = xn[r];
+    if constexpr (P == 16) {
+      // FP16: accumulate by fused multiply-add chains (a quarter fewer instructions)
+      if constexpr (K > 0) su3_mv_add(U, x, acc[r]);
+      else su3_mv_dag_sub(U, x, acc[r]);
+    } else {
       cx<R> y[3];
       if constexpr (K > 0) {
         su3_mv(U, x, y);

@@ -96,8 +96,13 @@ __device__ __forceinline__ void hop_fwd(const WilsonArgs& A, const int c[4], int
 #pragma unroll
         for (int i = 0; i < 6; ++i) h[i] = -h[i];
       }
-      su3_mv(U, h, uh);
-      su3_mv(U, h + 3, uh + 3);
+      if constexpr (P == 16) {
+        su3_mv_chain(U, h, uh);
+        su3_mv_chain(U, h + 3, uh + 3);
+      } else {
+        su3_mv(U, h, uh);
+        su3_mv(U, h + 3, uh + 3);
+      }
       recon_add<MU, DAG ? 1 : -1>(acc[r], uh);
     }
   }
@@ -123,8 +128,13 @@ __device__ __forceinline__ void hop_bwd(const WilsonArgs& A, const int c[4], int
 #pragma unroll
         for (int i = 0; i < 6; ++i) h[i] = -h[i];
       }
-      su3_mv_dag(U, h, uh);
-      su3_mv_dag(U, h + 3, uh + 3);
+      if constexpr (P == 16) {
+        su3_mv_dag_chain(U, h, uh);
+        su3_mv_dag_chain(U, h + 3, uh + 3);
+      } else {
+        su3_mv_dag(U, h, uh);
+        su3_mv_dag(U, h + 3, uh + 3);
+      }
       recon_add<MU, DAG ? -1 : 1>(acc[r], uh);
     }
   }
@@ -359,7 +369,7 @@ inline void launch_one(const WilsonArgs& A, int bs, hipStream_t s) {
 // epilogues with register-blocked variants (NR > 1)
 constexpr bool epi_blocked(int epi) {
   return epi == EPI_CLOVINV || epi == EPI_XMY_CLOVINV || epi == EPI_XPAY || epi == EPI_XPAY_G5 || epi == EPI_CHEB ||
-         epi == EPI_XMY_RTS;
+         epi == EPI_XMY_RTS || epi == EPI_SITE;
 }
 
 template <int P, int NE, int EPI>
@@ -403,7 +413,7 @@ inline int launch_epi(const WilsonArgs& A, int nr, int bs, hipStream_t s) {
       case EPI_CLOVINV: return launch_nr<P, NE, EPI_CLOVINV>(A, nr, bs, s);
       case EPI_XMY_CLOVINV: return launch_nr<P, NE, EPI_XMY_CLOVINV>(A, nr, bs, s);
       case EPI_XMY_RTS: return launch_nr<P, NE, EPI_XMY_RTS>(A, nr, bs, s);
-      case EPI_SITE: return launch_nr<P, NE, EPI_SITE>(A, 1, bs, s);
+      case EPI_SITE: return launch_nr<P, NE, EPI_SITE>(A, nr, bs, s);
       default: break;
     }
   }

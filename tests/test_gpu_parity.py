@@ -366,21 +366,23 @@ FORCES_H = FORCES + [f"3,{_blk(2, 3, 5)}", f"4,{_blk(4, 2, 2)},1,1"]   # 6x4x6x1
 @pytest.mark.parametrize("prec", [64, 32, 16])
 def test_column_blocking_bitwise_identical(ctx, prec, monkeypatch):
     """Every (columns per thread, block size) launch shape the tuner can pick
-    gives bitwise-identical results (7 columns: ragged column groups)."""
+    gives bitwise-identical results (7 columns: ragged column groups); for the
+    twisted clover both the Schur operator and the full D (site term)."""
     Lx = (6, 6, 4, 10)
     U, f = _wilson_setup(ctx, Lx, 131)
     psi = synth.gaussian_spinor(Lx, 7, 132)
     if prec == 16:
-        act, op = L.action(L.LQ_OVERLAP, m=0.0, rho=1.5, cheb_N=2, cheb_a=0.3, cheb_b=48.0), L.LQ_OP_HW
+        act, ops = L.action(L.LQ_OVERLAP, m=0.0, rho=1.5, cheb_N=2, cheb_a=0.3, cheb_b=48.0), [L.LQ_OP_HW]
     else:
-        act, op = L.action(L.LQ_TM_CLOVER, m=-0.0695, mu=0.01, c_sw=1.0509), L.LQ_OP_SCHUR
+        act, ops = L.action(L.LQ_TM_CLOVER, m=-0.0695, mu=0.01, c_sw=1.0509), [L.LQ_OP_SCHUR, L.LQ_OP_D]
     try:
-        outs = []
-        for force in FORCES_W:
-            monkeypatch.setenv("LQ_TUNE_FORCE", force)
-            outs.append(L.lq_apply(ctx, act, f, op, prec, psi))
-        for o in outs[1:]:
-            assert np.array_equal(o, outs[0])
+        for op in ops:
+            outs = []
+            for force in FORCES_W:
+                monkeypatch.setenv("LQ_TUNE_FORCE", force)
+                outs.append(L.lq_apply(ctx, act, f, op, prec, psi))
+            for o in outs[1:]:
+                assert np.array_equal(o, outs[0])
     finally:
         L.lq_field_free(f)
 
