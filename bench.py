@@ -118,19 +118,22 @@ def family_roofline(kernels, families):
             "share_of_step": None}
 
 
-# Sources that define the stencil kernels; measured HBM traffic is reported
-# only while they are unchanged since the counters were taken.
-KERNEL_SOURCES = ["paper_2201_09004_amd/csrc/lq_common.h", "paper_2201_09004_amd/csrc/lq_kernels.h",
-                  "paper_2201_09004_amd/csrc/wilson_impl.h", "paper_2201_09004_amd/csrc/wilson32.hip",
-                  "paper_2201_09004_amd/csrc/wilson16.hip", "paper_2201_09004_amd/csrc/wilson.hip",
-                  "paper_2201_09004_amd/csrc/staggered.hip", "paper_2201_09004_amd/csrc/blas.hip"]
+# Sources that define each workload's measured kernels; its measured HBM
+# traffic is reported only while they are unchanged since the counters were taken.
+_CSRC = "paper_2201_09004_amd/csrc/"
+_COMMON_SOURCES = ["lq_common.h", "lq_kernels.h", "blas.hip"]
+KERNEL_SOURCES = {
+    "tm_clover_eo_bicgstab_24x24x24x64_12rhs": _COMMON_SOURCES + ["wilson_impl.h", "wilson32.hip", "wilson.hip"],
+    "overlap_sign_cheb200_24x24x24x64_12rhs": _COMMON_SOURCES + ["wilson_impl.h", "wilson16.hip", "wilson.hip"],
+    "hisq_multishift_cg_32x32x32x96_12rhs_8mass": _COMMON_SOURCES + ["staggered.hip"],
+}
 
 
-def kernel_sources_sha():
+def kernel_sources_sha(workload):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
+    for f in KERNEL_SOURCES[workload]:
+        with open(os.path.join(ROOT, _CSRC + f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -145,7 +148,7 @@ def measured_traffic(kernel, workload):
     with open(path) as f:
         t = json.load(f)
     e = t.get(workload, {}).get(kernel)
-    if not e or e.get("sources_sha256") != kernel_sources_sha():
+    if not e or e.get("sources_sha256") != kernel_sources_sha(workload):
         return None
     return e["hbm_bytes_per_launch"]
 

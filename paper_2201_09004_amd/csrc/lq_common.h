@@ -51,15 +51,16 @@ template <typename R> __host__ __device__ __forceinline__ void fmac(cx<R>& a, cx
   a.re += b.re * c.re + b.im * c.im;
   a.im += b.re * c.im - b.im * c.re;
 }
-// The same as chains of four fused multiply-adds into a: a += b c, a += conj(b) c
-// and a -= conj(b) c.  Written as a + (x - y), as fma and fmac are, each part
-// costs a multiply, an FMA and an add; the chains take 4 instead of 6
-// instructions per complex multiply-add.  The FP16 stencils use them: there the
-// conversions fold into the FMAs (v_fma_mix_f32) and the instruction issue rate
-// bounds the kernel.  The FP32 and FP64 stencils keep fma / fmac, with which
-// the compiler's register allocation and occupancy measured faster.
+// real fused multiply-add, one rounding (v_fma_f32 / v_fma_f64)
 __host__ __device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __host__ __device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// a += b c and a += conj(b) c as chains of four fused multiply-adds into a.
+// Written as a + (x - y), as fma and fmac are, each real part costs a multiply,
+// an FMA and an add; the chains take 4 instead of 6 instructions per complex
+// multiply-add.  The FP16 Wilson stencils use them (their operands are
+// converted inside the FMA, v_fma_mix_f32, and instruction issue bounds the
+// kernel); the FP32 and FP64 stencils keep fma / fmac, with which the compiler's
+// register allocation and occupancy measured faster.
 template <typename R> __host__ __device__ __forceinline__ void cmadd(cx<R>& a, cx<R> b, cx<R> c) {
   a.re = fmar(b.re, c.re, a.re);
   a.re = fmar(-b.im, c.im, a.re);
@@ -72,12 +73,17 @@ template <typename R> __host__ __device__ __forceinline__ void cmadd_conj(cx<R>&
   a.im = fmar(b.re, c.im, a.im);
   a.im = fmar(-b.im, c.re, a.im);
 }
-template <typename R> __host__ __device__ __forceinline__ void cmsub_conj(cx<R>& a, cx<R> b, cx<R> c) {
-  a.re = fmar(-b.re, c.re, a.re);
-  a.re = fmar(-b.im, c.im, a.re);
-  a.im = fmar(-b.re, c.im, a.im);
-  a.im = fmar(b.im, c.re, a.im);
+// FP16 operands packed as (re, im) pairs of halves: dot2h(a, b, c) = a.re b.re +
+// a.im b.im + c in FP32 by v_dot2_f32_f16 (the product of two FP16 numbers is
+// exact in FP32), so with m = (m.re, m.im) one real part of m x is one
+// instruction: Re(m x) = dot2h((m.re, -m.im), x), Im(m x) = dot2h((m.im, m.re), x).
+typedef _Float16 half2_v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float dot2h(unsigned a, unsigned b, float c) {
+  return __builtin_amdgcn_fdot2(__builtin_bit_cast(half2_v, a), __builtin_bit_cast(half2_v, b), c, false);
 }
+__device__ __forceinline__ unsigned swap_halves(unsigned w) { return (w >> 16) | (w << 16); }
+// sign bits of the upper (im) and the lower (re) half
+constexpr unsigned kSignHi = 0x80000000u, kSignLo = 0x00008000u;
 template <typename R> __host__ __device__ __forceinline__ cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
 template <typename R> __host__ __device__ __forceinline__ cx<R> times_mi(cx<R> a) { return {a.im, -a.re}; }
 
@@ -403,7 +409,7 @@ __device__ __forceinline__ void su3_mv_dag(const cx<R>* U, const cx<R>* x, cx<R>
     y[a] = s;
   }
 }
-// the same with fused multiply-add chains (FP16 stencils)
+// the same with fused multiply-add chains (FP16 Wilson stencils)
 template <typename R>
 __device__ __forceinline__ void su3_mv_chain(const cx<R>* U, const cx<R>* x, cx<R>* y) {
 #pragma unroll
@@ -422,25 +428,6 @@ __device__ __forceinline__ void su3_mv_dag_chain(const cx<R>* U, const cx<R>* x,
     cmadd_conj(s, U[3 + a], x[1]);
     cmadd_conj(s, U[6 + a], x[2]);
     y[a] = s;
-  }
-}
-// y += U x and y -= U^dag x, accumulating in place (36 fused multiply-adds)
-template <typename R>
-__device__ __forceinline__ void su3_mv_add(const cx<R>* U, const cx<R>* x, cx<R>* y) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    cmadd(y[a], U[3 * a], x[0]);
-    cmadd(y[a], U[3 * a + 1], x[1]);
-    cmadd(y[a], U[3 * a + 2], x[2]);
-  }
-}
-template <typename R>
-__device__ __forceinline__ void su3_mv_dag_sub(const cx<R>* U, const cx<R>* x, cx<R>* y) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    cmsub_conj(y[a], U[a], x[0]);
-    cmsub_conj(y[a], U[3 + a], x[1]);
-    cmsub_conj(y[a], U[6 + a], x[2]);
   }
 }
 

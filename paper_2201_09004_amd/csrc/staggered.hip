@@ -16,6 +16,7 @@
 // One thread owns one site and NR consecutive columns: the 16 links of a site
 // are loaded once for all NR columns (bitwise-identical per-column results
 // for every NR), and the NR neighbour loads of a hop are issued together.
+// FP16 products are formed by v_dot2_f32_f16 on the packed halves.
 #include <type_traits>
 
 #include "lq_common.h"
@@ -28,31 +29,66 @@ __device__ __forceinline__ void stag_hop1(const StagArgs& A, const int c[4], int
                                           cx<R> (*acc)[3]) {
   const Geom& g = A.g;
   const int pin = par ^ 1;
-  cx<R> U[9];
   const void* links = LONG ? A.lng : A.fat;
   const int nb = nb_cb(c, MU, K, g);
-  if constexpr (K > 0) load_link<P, 9>(links, g.Vh, par, MU, cb, U);
-  else load_link<P, 9>(links, g.Vh, pin, MU, nb, U);
-  // all NR columns' loads in flight at once (columns past the last are
-  // clamped to a valid one and their results dropped)
-  cx<R> xn[NR][3];
+  if constexpr (P == 16) {
+    // FP16 products by v_dot2_f32_f16 (dot2h); the link is rearranged once for
+    // all NR columns so that each real part is one dot2h on the neighbour's
+    // packed halves x_j = (re, im), and the neighbour's site norm scales the sum:
+    //   U x:      re = dot2h((u.re, -u.im), x_j), im = dot2h((u.im, u.re), x_j)
+    //   U^dag x:  re = dot2h((u.re, u.im), x_j),  im = dot2h((-u.im, u.re), x_j)
+    unsigned Ur[9], Ui[9];
+    {
+      const unsigned* lp = (const unsigned*)links;
+      const int grp = (K > 0 ? par : pin) * 4 + MU;
 #pragma unroll
-  for (int r = 0; r < NR; ++r) IO<P, 3>::load(A.in, blk_index(A.in, min(col0 + r, A.ncol - 1), pin), nb, xn[r]);
+      for (int e = 0; e < 9; ++e) {
+        const unsigned u = ldx<true>(lp + tix(grp, e, 9, K > 0 ? cb : nb, g.Vh));
+        Ur[e] = K > 0 ? u ^ kSignHi : u;
+        Ui[e] = K > 0 ? swap_halves(u) : swap_halves(u) ^ kSignLo;
+      }
+    }
+    uint4 xn[NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const cx<R>* x = xn[r];
-    if constexpr (P == 16) {
-      // FP16: accumulate by fused multiply-add chains (a quarter fewer instructions)
-      if constexpr (K > 0) su3_mv_add(U, x, acc[r]);
-      else su3_mv_dag_sub(U, x, acc[r]);
-    } else {
+    for (int r = 0; r < NR; ++r)
+      xn[r] = ldx<false>((const uint4*)A.in.data + tix(blk_index(A.in, min(col0 + r, A.ncol - 1), pin), 0, 1, nb,
+                                                      A.in.Vh));
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const float n = __uint_as_float(xn[r].w);
+      const unsigned w[3] = {xn[r].x, xn[r].y, xn[r].z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        float yr = 0.f, yi = 0.f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const int e = K > 0 ? 3 * a + j : 3 * j + a;
+          yr = dot2h(Ur[e], w[j], yr);
+          yi = dot2h(Ui[e], w[j], yi);
+        }
+        const float sn = K > 0 ? n : -n;
+        acc[r][a].re = fmar(sn, yr, acc[r][a].re);
+        acc[r][a].im = fmar(sn, yi, acc[r][a].im);
+      }
+    }
+  } else {
+    cx<R> U[9];
+    if constexpr (K > 0) load_link<P, 9>(links, g.Vh, par, MU, cb, U);
+    else load_link<P, 9>(links, g.Vh, pin, MU, nb, U);
+    // all NR columns' loads in flight at once (columns past the last are
+    // clamped to a valid one and their results dropped)
+    cx<R> xn[NR][3];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) IO<P, 3>::load(A.in, blk_index(A.in, min(col0 + r, A.ncol - 1), pin), nb, xn[r]);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
       cx<R> y[3];
       if constexpr (K > 0) {
-        su3_mv(U, x, y);
+        su3_mv(U, xn[r], y);
 #pragma unroll
         for (int a = 0; a < 3; ++a) acc[r][a] = acc[r][a] + y[a];
       } else {
-        su3_mv_dag(U, x, y);
+        su3_mv_dag(U, xn[r], y);
 #pragma unroll
         for (int a = 0; a < 3; ++a) acc[r][a] = acc[r][a] - y[a];
       }
