@@ -417,6 +417,9 @@ def bench_tm(args, L, torch):
         fp64 = {"solves_per_s": 1.0 / t64, "seconds_median_of_3": t64, "seconds_all": runs, "iters": st64["iters"],
                 "true_rel_res": st64["true_rel_res"], "warmup": 1}
         log("fp64", fp64)
+        if mg:
+            # the multigrid propagator is mixed precision and batched as well
+            mg["speedup_vs_fp64_single_column"] = round(mg["solves_per_s"] / fp64["solves_per_s"], 3)
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline")
