@@ -69,7 +69,7 @@ typedef struct lq_field lq_field;
 typedef struct lq_server lq_server;
 
 typedef struct {
-  int32_t L[4];           /* Lx, Ly, Lz, Lt: all even */
+  int32_t L[4];           /* Lx, Ly, Lz, Lt: all even; Lx Ly Lz Lt / 2 <= 2^31 / 64 (else LQ_EINVAL) */
   int32_t t_antiperiodic; /* 1: antiperiodic fermion time boundary (default) */
 } lq_geom;
 
@@ -165,6 +165,12 @@ lq_status lq_hisq_load(lq_ctx *ctx, const lq_geom *geom, const double *fat, cons
 lq_status lq_hisq_load_dev(lq_ctx *ctx, const lq_geom *geom, const double *fat_dev, const double *lng_dev,
                            void *stream, lq_field **g);
 lq_status lq_field_free(lq_field *g);
+
+/* Most columns one call may carry: n_rhs, times n_shift for several masses and
+ * times 2 for the chirally projected overlap solve (its two chiral sectors).
+ * The vector kernels put the columns on the second dimension of their launch
+ * grid.  Larger calls are refused with LQ_EINVAL before any data is read. */
+#define LQ_MAX_COLUMNS 65535
 
 /* Apply one operator (op codes above) once to n_rhs columns, with field
  * storage of prec_bits = 64, 32 or 16 (FP16: values scaled by a per-site FP32

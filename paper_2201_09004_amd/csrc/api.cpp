@@ -213,6 +213,7 @@ static int check_apply(lq_ctx* c, const lq_action* act, const lq_field* g, int p
   if ((prec & ~LQ_PREC_RECON12) != 64 && (prec & ~LQ_PREC_RECON12) != 32 && (prec & ~LQ_PREC_RECON12) != 16)
     return fail(LQ_EINVAL, "prec_bits must be 64, 32 or 16 (optionally | LQ_PREC_RECON12)");
   if (n_rhs < 0) return fail(LQ_EINVAL, "n_rhs must be >= 0");
+  if (n_rhs > LQ_MAX_COLUMNS) return fail(LQ_EINVAL, "n_rhs above LQ_MAX_COLUMNS");
   if (n_rhs > 0 && (!in || !out)) return fail(LQ_EINVAL, "NULL field pointer");
   return 0;
 }
@@ -266,6 +267,13 @@ static int check_solve(lq_ctx* c, const lq_action* act, const lq_field* g, const
     return fail(LQ_EINVAL, "sloppy_bits must be 64, 32 or 16");
   if (!(prm->tol >= 0) || prm->tol >= 1.0) return fail(LQ_EINVAL, "tol must be in [0, 1)");
   if (prm->n_shift < 0 || prm->n_shift > 64) return fail(LQ_EINVAL, "n_shift out of range");
+  {
+    // columns the solver carries: the masses, and the overlap solve's two chiral sectors
+    const int64_t cols = (int64_t)n_rhs * (prm->n_shift > 1 ? prm->n_shift : 1) *
+                         (act->kind == LQ_OVERLAP && prm->solver == 0 ? 2 : 1);
+    if (cols > LQ_MAX_COLUMNS)
+      return fail(LQ_EINVAL, "n_rhs (x n_shift, x 2 for the overlap sectors) above LQ_MAX_COLUMNS");
+  }
   if (prm->n_shift > 1 && act->kind != LQ_HISQ && act->kind != LQ_OVERLAP)
     return fail(LQ_EINVAL, "several masses are implemented for HISQ and overlap");
   if (prm->solver < 0 || prm->solver > 3) return fail(LQ_EINVAL, "solver must be 0, 1, 2 or 3");
@@ -354,6 +362,7 @@ lq_status lq_mg_apply(lq_ctx* c, const lq_action* act, const lq_field* g, int op
   int e = check_action(act, g);
   if (e) return (lq_status)e;
   if (n_rhs < 0) return (lq_status)fail(LQ_EINVAL, "n_rhs must be >= 0");
+  if (n_rhs > LQ_MAX_COLUMNS) return (lq_status)fail(LQ_EINVAL, "n_rhs above LQ_MAX_COLUMNS");
   if (n_rhs > 0 && (!in || !out)) return (lq_status)fail(LQ_EINVAL, "NULL array");
   hipSetDevice(c->device);
   return (lq_status)mg_apply_host(c, act, const_cast<lq_field*>(g), op, prec, n_rhs, in, out, c->stream);

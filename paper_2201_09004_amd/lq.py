@@ -22,6 +22,7 @@ LQ_OK, LQ_EINVAL, LQ_ENOMEM, LQ_EDEVICE, LQ_ENOCONV, LQ_EBREAKDOWN, LQ_ENUMERIC,
     0, -1, -2, -3, -4, -5, -6, -7, -8
 LQ_WILSON, LQ_TM_CLOVER, LQ_HISQ, LQ_OVERLAP = 0, 1, 2, 3
 LQ_PREC_RECON12 = 0x100
+LQ_MAX_COLUMNS = 65535
 (LQ_OP_D, LQ_OP_DDAG, LQ_OP_HOP, LQ_OP_SITE, LQ_OP_SITE_INV, LQ_OP_SCHUR, LQ_OP_HW, LQ_OP_SIGN,
  LQ_OP_NORMAL_EVEN) = range(9)
 

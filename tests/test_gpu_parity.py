@@ -6,6 +6,8 @@ and 1e-12 (composite operators), FP32 storage 1e-6, FP16 storage with per-site
 norms 3e-3.  Solutions: FP64 relative true residual <= 1e-10 computed with the
 oracle operator.  Lattices span several 128-site tiles plus a ragged tail.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -142,6 +144,46 @@ def test_empty_and_invalid(ctx):
         assert e.value.code == L.LQ_EINVAL
     finally:
         L.lq_field_free(f)
+
+
+def test_size_limits_are_refused_before_any_data_is_read(ctx):
+    """The largest sizes the C ABI accepts: a lattice with V/2 above 2^31/64 sites
+    and calls with more than LQ_MAX_COLUMNS columns (n_rhs, times the masses,
+    times the two chiral sectors of the overlap solve) return LQ_EINVAL before
+    the (here far too small) data arrays are touched."""
+    tiny = np.zeros(16, np.complex128)
+    with pytest.raises(L.LqError) as e:
+        L.lq_gauge_load(ctx, (2048, 2048, 2048, 64), tiny)
+    assert e.value.code == L.LQ_EINVAL and "too large" in str(e.value)
+    Lx = (4, 4, 4, 4)
+    U, f = _wilson_setup(ctx, Lx, 43)
+    lib = L.load()
+    st = L.lq_stats()
+    try:
+        act = L.action(L.LQ_WILSON, m=0.1)
+        code = lib.lq_apply(ctx, ctypes.byref(act), f, L.LQ_OP_D, 64, L.LQ_MAX_COLUMNS + 1, L._ptr(tiny), L._ptr(tiny))
+        assert code == L.LQ_EINVAL and "LQ_MAX_COLUMNS" in L.last_error()
+        prm = L.params(tol=1e-10)
+        code = lib.lq_solve(ctx, ctypes.byref(act), f, ctypes.byref(prm), L.LQ_MAX_COLUMNS + 1, L._ptr(tiny),
+                            L._ptr(tiny), ctypes.byref(st))
+        assert code == L.LQ_EINVAL and "LQ_MAX_COLUMNS" in L.last_error()
+        # the overlap solve carries both chiral sectors of every column
+        ov = L.action(L.LQ_OVERLAP, m=0.015, rho=1.5, cheb_N=8, cheb_a=0.3, cheb_b=48.0)
+        code = lib.lq_solve(ctx, ctypes.byref(ov), f, ctypes.byref(prm), L.LQ_MAX_COLUMNS // 2 + 1, L._ptr(tiny),
+                            L._ptr(tiny), ctypes.byref(st))
+        assert code == L.LQ_EINVAL and "LQ_MAX_COLUMNS" in L.last_error()
+    finally:
+        L.lq_field_free(f)
+    V, Wl = synth.hisq_fields(Lx, 44)
+    h = L.lq_hisq_load(ctx, Lx, V, Wl)
+    try:
+        # several masses multiply the columns: 8 masses x 8192 right-hand sides
+        prm = L.params(tol=1e-10, masses=[0.01 * (k + 1) for k in range(8)])
+        code = lib.lq_solve(ctx, ctypes.byref(L.action(L.LQ_HISQ, m=0.01)), h, ctypes.byref(prm), 8192,
+                            L._ptr(tiny), L._ptr(tiny), ctypes.byref(st))
+        assert code == L.LQ_EINVAL and "LQ_MAX_COLUMNS" in L.last_error()
+    finally:
+        L.lq_field_free(h)
 
 
 # ------------------------------------------------------------------ HISQ
