@@ -235,9 +235,6 @@ __device__ __forceinline__ double sum_r(const double* p, int gridx, int k) {
   __syncthreads();  // wsum is reused by the next sum
   return t;
 }
-__device__ __forceinline__ cx<double> sum_c(const double* p, int gridx, int k) {
-  return {sum_r(p, gridx, k), sum_r(p, gridx, k + 1)};
-}
 __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
   const double d = b.re * b.re + b.im * b.im;
   return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};

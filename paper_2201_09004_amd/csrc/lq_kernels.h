@@ -13,8 +13,10 @@ namespace lq {
 // ------------------------------------------------------------ Wilson type
 // EPI_XMY_RTS: EPI_XMY_CLOVINV plus the per-column reductions <out, x> and
 // |out|^2 written as wave partials red[(col * ntile + tile) * 4 + k]
-// (ntile = 64-site tiles of the launch).
-enum { EPI_HOP = 0, EPI_XPAY, EPI_XPAY_G5, EPI_CLOVINV, EPI_XMY_CLOVINV, EPI_SITE, EPI_CHEB, EPI_XMY_RTS };
+// (ntile = 64-site tiles of the launch).  EPI_CLOVINV_XPAY: A^{-1} (x + k hop)
+// (the even-odd source and the odd-site reconstruction of the twisted clover).
+enum { EPI_HOP = 0, EPI_XPAY, EPI_XPAY_G5, EPI_CLOVINV, EPI_XMY_CLOVINV, EPI_SITE, EPI_CHEB, EPI_XMY_RTS,
+       EPI_CLOVINV_XPAY };
 
 struct WilsonArgs {
   Geom g;
@@ -169,7 +171,6 @@ int launch_mg_site_inverse(const MgGeom& m, const void* Dc64, void* Ahat64, void
 int launch_mg_site_mul(const MgGeom& m, const void* Dc64, void* Ahat64, hipStream_t s);
 int launch_mg_gather(const MgGeom& m, FieldRef fine, void* Q64, hipStream_t s);
 int launch_mg_orth(const MgGeom& m, void* Q64, int* bad, hipStream_t s);
-int launch_mg_probe_source(const MgGeom& m, FieldRef coarse, int ncol, int k0, int cls, hipStream_t s);
 int launch_mg_probe_restrict(const MgGeom& m, const void* Q64, FieldRef fine, int ncol, int k0, int cls, void* Dc64,
                              hipStream_t s);
 int launch_mg_narrow(const void* src64, void* dst32, int64_t n_complex, hipStream_t s);

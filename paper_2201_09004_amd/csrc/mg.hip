@@ -634,19 +634,6 @@ __global__ void __launch_bounds__(256) mg_orth_kernel(MgGeom m, double2* Q, int*
   }
 }
 
-// probe sources: column kk is the coarse unit vector of component k0 + kk on
-// every aggregate of coarse parity class cls
-__global__ void __launch_bounds__(256) mg_probe_source_kernel(MgGeom m, FieldRef coarse, int ncol, int k0, int cls) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int n2 = 2 * m.nv;
-  if (gid >= (int64_t)ncol * m.Vc * n2) return;
-  const int d = (int)(gid % n2);
-  const int Y = (int)((gid / n2) % m.Vc);
-  const int col = (int)(gid / ((int64_t)n2 * m.Vc));
-  const double v = (d == k0 + col && m.cpar[Y] == cls) ? 1.0 : 0.0;
-  cst<64>(coarse, m, col, Y, d, cx<double>{v, 0.0});
-}
-
 // Columns k0.. of Dc from D applied to the probe sources of class cls: an
 // aggregate of class cls restricts its whole block into the self term; an
 // aggregate whose class differs in the bit of direction mu only receives the
@@ -947,13 +934,6 @@ int launch_mg_gather(const MgGeom& m, FieldRef fine, void* Q64, hipStream_t s) {
 
 int launch_mg_orth(const MgGeom& m, void* Q64, int* bad, hipStream_t s) {
   mg_orth_kernel<<<m.Vc * 2, 256, 0, s>>>(m, (double2*)Q64, bad);
-  return hipGetLastError() == hipSuccess ? 0 : -2;
-}
-
-int launch_mg_probe_source(const MgGeom& m, FieldRef coarse, int ncol, int k0, int cls, hipStream_t s) {
-  const int64_t n = (int64_t)ncol * m.Vc * 2 * m.nv;
-  if (n <= 0) return 0;
-  mg_probe_source_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(m, coarse, ncol, k0, cls);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -503,14 +503,14 @@ static int run_wilson(OpEnv& e, WilsonArgs& A, int n_fields, int clov_mats, int 
   A.recon = (e.recon && A.prec != 64) ? 1 : 0;
   if (!A.links) return fail(LQ_EDEVICE, "links not packed");
   const int nsite = A.par_out == 2 ? 2 * A.g.Vh : A.g.Vh;
-  static const char* epi_names[] = {"hop", "xpay", "xpay_g5", "clovinv", "xmy", "site", "cheb", "xmyt"};
+  static const char* epi_names[] = {"hop", "xpay", "xpay_g5", "clovinv", "xmy", "site", "cheb", "xmyt", "clovinv_x"};
   char name[48];
   snprintf(name, sizeof(name), "wilson%d_%s", A.prec, epi_names[A.epi]);
   char key[160];
   snprintf(key, sizeof(key), "%s_r%d_d%d_n%d_v%d_p%d", name, A.recon, A.dag, col_bucket(A.ncol), A.g.Vh, A.par_out);
   const bool blocked = !A.dag && (A.epi == EPI_CLOVINV || A.epi == EPI_XMY_CLOVINV || A.epi == EPI_XPAY ||
                                   A.epi == EPI_XPAY_G5 || A.epi == EPI_CHEB || A.epi == EPI_XMY_RTS ||
-                                  A.epi == EPI_SITE);
+                                  A.epi == EPI_SITE || A.epi == EPI_CLOVINV_XPAY);
   const int out_npar = A.out.npar;
   // timed under the kernel's name and under name_n<columns> (solvers that drop
   // converged columns launch the same kernel at several widths)
@@ -619,8 +619,8 @@ int tm_schur_source(OpEnv& e, Vec& bhat_e, const Vec& b) {
   const Clover* c = get_clover(e);
   const Geom& g = e.f->g;
   Vec t_o = make_vec(g, prec, 12, b.ncol, 1, 1, e.s);
-  Vec u_e = make_vec(g, prec, 12, b.ncol, 1, 0, e.s);
-  if (!t_o.ok() || !u_e.ok()) return fail(LQ_ENOMEM, "schur source buffers");
+  if (!t_o.ok()) return fail(LQ_ENOMEM, "schur source buffers");
+  // t_o = A_oo^-1 b_o, then b_hat_e = A_ee^-1 (b_e + 1/2 hop(t_o)) in one stencil
   if (launch_site(g, prec, c->H[pidx(prec)], c->Ainv[pidx(prec)], e.act.mu, true, b.f, t_o.f, 1, b.ncol, e.s))
     return fail(LQ_EDEVICE, "site");
   WilsonArgs A{};
@@ -628,17 +628,13 @@ int tm_schur_source(OpEnv& e, Vec& bhat_e, const Vec& b) {
   A.ncol = b.ncol;
   A.links = links_for(e, prec);
   A.in = t_o.f;
-  A.out = u_e.f;
+  A.out = bhat_e.f;
   A.x = b.f;
-  A.a = 1.0;
+  A.clov_inv = c->Ainv[pidx(prec)];
   A.k_hop = 0.5;
   A.par_out = 0;
-  A.epi = EPI_XPAY;
-  r = run_wilson(e, A, 3, 0, 48);
-  if (r) return r;
-  if (launch_site(g, prec, c->H[pidx(prec)], c->Ainv[pidx(prec)], e.act.mu, true, u_e.f, bhat_e.f, 0, b.ncol, e.s))
-    return fail(LQ_EDEVICE, "site");
-  return 0;
+  A.epi = EPI_CLOVINV_XPAY;
+  return run_wilson(e, A, 3, 2, 600);
 }
 
 int tm_schur_reconstruct(OpEnv& e, Vec& x, const Vec& x_e, const Vec& b) {
@@ -647,9 +643,6 @@ int tm_schur_reconstruct(OpEnv& e, Vec& x, const Vec& x_e, const Vec& b) {
   if (!r) r = ensure_clover(e, prec);
   if (r) return r;
   const Clover* c = get_clover(e);
-  const Geom& g = e.f->g;
-  Vec u_o = make_vec(g, prec, 12, b.ncol, 1, 1, e.s);
-  if (!u_o.ok()) return fail(LQ_ENOMEM, "reconstruct buffers");
   WilsonArgs A{};
   A.prec = prec;
   A.ncol = b.ncol;
@@ -664,16 +657,14 @@ int tm_schur_reconstruct(OpEnv& e, Vec& x, const Vec& x_e, const Vec& b) {
   A.epi = EPI_XPAY;
   r = run_wilson(e, A, 2, 0, 0);
   if (r) return r;
-  // u_o = b_o - D_oe x_e = b_o + 1/2 hop(x_e)
-  A.out = u_o.f;
+  // x_o = A_oo^-1 (b_o - D_oe x_e) = A_oo^-1 (b_o + 1/2 hop(x_e)) in one stencil
+  A.out = x.f;
   A.x = b.f;
+  A.clov_inv = c->Ainv[pidx(prec)];
   A.k_hop = 0.5;
   A.par_out = 1;
-  r = run_wilson(e, A, 3, 0, 48);
-  if (r) return r;
-  if (launch_site(g, prec, c->H[pidx(prec)], c->Ainv[pidx(prec)], e.act.mu, true, u_o.f, x.f, 1, b.ncol, e.s))
-    return fail(LQ_EDEVICE, "site");
-  return 0;
+  A.epi = EPI_CLOVINV_XPAY;
+  return run_wilson(e, A, 3, 2, 600);
 }
 
 // ------------------------------------------------------------------ overlap

@@ -12,7 +12,7 @@ extern template int launch_wilson_prec<16>(const WilsonArgs& A, int nr, int bs, 
 
 int launch_wilson(const WilsonArgs& A, hipStream_t s) {
   if (A.prec == 16 && (A.epi == EPI_CLOVINV || A.epi == EPI_XMY_CLOVINV || A.epi == EPI_SITE ||
-                       A.epi == EPI_XMY_RTS))
+                       A.epi == EPI_XMY_RTS || A.epi == EPI_CLOVINV_XPAY))
     return -1;
   const int nr = A.nr > 0 ? A.nr : 1;
   if (!traversal_valid(A.g, A.slab)) return -1;

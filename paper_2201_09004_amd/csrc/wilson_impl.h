@@ -8,6 +8,7 @@
 //   EPI_XPAY        out = a x + k hop                 (Wilson D)
 //   EPI_XPAY_G5     out = g5 (a x + k hop)            (H_W = g5 D_W(-rho), sec. 2.3)
 //   EPI_CLOVINV     out = A^{-1} (k hop)              (first half of the Schur operator)
+//   EPI_CLOVINV_XPAY out = A^{-1} (x + k hop)         (even-odd source, odd-site reconstruction)
 //   EPI_XMY_CLOVINV out = x - A^{-1} (k hop)          (second half)
 //   EPI_SITE        out = A x + k hop,  A = H + i mu g5 (full twisted-clover D)
 //   EPI_CHEB        out = s1 g5 (a x + k hop) + ck v + s2 b1 - b2   (one Clenshaw step)
@@ -269,7 +270,17 @@ wilson_kernel(WilsonArgs A) {
 #pragma unroll
     for (int i = 0; i < 12; ++i) acc[r][i] = k * acc[r][i];
 
-  if constexpr (EPI == EPI_CLOVINV || XMY) {
+  if constexpr (EPI == EPI_CLOVINV_XPAY) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r >= nv) continue;
+      cx<R> x[12];
+      IO<P, 12>::template load<true>(A.x, blk_index(A.x, col0 + r, par), cb, x);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) acc[r][i] = acc[r][i] + x[i];
+    }
+  }
+  if constexpr (EPI == EPI_CLOVINV || XMY || EPI == EPI_CLOVINV_XPAY) {
     apply_full6_nr<P, NR>(A.clov_inv, A.g.Vh, par, 0, cb, nv, acc, 0);
     apply_full6_nr<P, NR>(A.clov_inv, A.g.Vh, par, 1, cb, nv, acc, 6);
   }
@@ -281,7 +292,7 @@ wilson_kernel(WilsonArgs A) {
     if (r >= nv) continue;
     const int col = col0 + r;
     cx<R> out[12];
-    if constexpr (EPI == EPI_HOP || EPI == EPI_CLOVINV) {
+    if constexpr (EPI == EPI_HOP || EPI == EPI_CLOVINV || EPI == EPI_CLOVINV_XPAY) {
 #pragma unroll
       for (int i = 0; i < 12; ++i) out[i] = acc[r][i];
     } else if constexpr (XMY) {
@@ -369,7 +380,7 @@ inline void launch_one(const WilsonArgs& A, int bs, hipStream_t s) {
 // epilogues with register-blocked variants (NR > 1)
 constexpr bool epi_blocked(int epi) {
   return epi == EPI_CLOVINV || epi == EPI_XMY_CLOVINV || epi == EPI_XPAY || epi == EPI_XPAY_G5 || epi == EPI_CHEB ||
-         epi == EPI_XMY_RTS || epi == EPI_SITE;
+         epi == EPI_XMY_RTS || epi == EPI_SITE || epi == EPI_CLOVINV_XPAY;
 }
 
 template <int P, int NE, int EPI>
@@ -413,6 +424,7 @@ inline int launch_epi(const WilsonArgs& A, int nr, int bs, hipStream_t s) {
       case EPI_CLOVINV: return launch_nr<P, NE, EPI_CLOVINV>(A, nr, bs, s);
       case EPI_XMY_CLOVINV: return launch_nr<P, NE, EPI_XMY_CLOVINV>(A, nr, bs, s);
       case EPI_XMY_RTS: return launch_nr<P, NE, EPI_XMY_RTS>(A, nr, bs, s);
+      case EPI_CLOVINV_XPAY: return launch_nr<P, NE, EPI_CLOVINV_XPAY>(A, nr, bs, s);
       case EPI_SITE: return launch_nr<P, NE, EPI_SITE>(A, nr, bs, s);
       default: break;
     }
