@@ -474,7 +474,7 @@ def bench_tm_mg(args, L, torch):
     act = L.action(L.LQ_TM_CLOVER, m=M, mu=MU, c_sw=CSW)
     block = tuple(int(v) for v in args.mg_block.split(","))
     mp = L.mg_params(block=block, n_vec=args.mg_nvec, coarse_tol=args.mg_coarse_tol, nu_post=args.mg_nu,
-                     setup_passes=args.mg_passes, gcr_kmax=args.mg_kmax, seed=11)
+                     setup_passes=args.mg_passes, gcr_kmax=args.mg_kmax, seed=11, nu_pre=args.mg_nu_pre)
     log("multigrid setup", block, args.mg_nvec)
     torch.cuda.synchronize()
     ts = time.perf_counter()
@@ -517,7 +517,7 @@ def bench_tm_mg(args, L, torch):
         "config": {"workload": "tm_clover_mg_gcr_24x24x24x64_12rhs", "lattice": list(TM_LAT), "n_rhs": n_rhs,
                    "m": M, "c_sw": CSW, "mu": MU, "sources": "point", "tol": 1e-10, "block": list(block),
                    "n_vec": args.mg_nvec, "coarse_tol": args.mg_coarse_tol, "nu_post": args.mg_nu,
-                   "setup_passes": args.mg_passes, "gcr_kmax": args.mg_kmax},
+                   "setup_passes": args.mg_passes, "gcr_kmax": args.mg_kmax, "nu_pre": args.mg_nu_pre},
         "setup_seconds": round(t_setup, 3), "setup_iters": setup["iters"],
         "roofline": roof, "cpu_baseline": None, "worst_true_rel_res": worst,
         "outer_iters": [s["iters"] for s in stats], "restarts": [s["reliable_updates"] for s in stats],
@@ -1077,6 +1077,7 @@ def main():
     ap.add_argument("--mg-coarse-tol", type=float, default=0.1, help="coarse solve tolerance (tm_mg)")
     ap.add_argument("--mg-nu", type=int, default=4, help="post-smoothing steps (tm_mg)")
     ap.add_argument("--mg-passes", type=int, default=2, help="setup inverse-iteration passes (tm_mg)")
+    ap.add_argument("--mg-nu-pre", type=int, default=0, help="pre-smoothing steps of the V-cycle (tm_mg)")
     ap.add_argument("--mg-kmax", type=int, default=8, help="outer GCR restart length (tm_mg)")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -275,7 +275,9 @@ lq_status lq_cheb_coeffs(double a, double b, int N, double *c);
  * LQ_ENOCONV), each direction from one V-cycle in FP32: restrict the residual,
  * solve the even-odd preconditioned coarse system by BiCGStab to coarse_tol (at
  * most coarse_maxiter iterations), prolong, then nu_post minimal-residual steps
- * on the even-odd preconditioned fine system.
+ * on the even-odd preconditioned fine system; with nu_pre > 0 the cycle first
+ * takes nu_pre such steps on the residual it is given and restricts the
+ * residual they leave.
  * Coarse vectors (lq_mg_apply): host [n_rhs][Vc][2][n_vec] complex, index 0 of
  * the chirality axis for gamma5 = +1 (spins 0, 1 of the chiral basis). */
 typedef struct {
@@ -290,6 +292,8 @@ typedef struct {
   const double *null_vecs; /* optional host [n_vec][V][4][3]: the near-null vectors themselves, no passes */
   int32_t nu_post;         /* minimal-residual smoothing steps on the fine level (0: 4) */
   int32_t gcr_kmax;        /* outer flexible GCR restart length (0: 8) */
+  int32_t nu_pre;          /* minimal-residual steps before the coarse correction (0: none) */
+  int32_t reserved;        /* must be 0 */
 } lq_mg_params;
 
 /* Computes and stores the hierarchy.  stats: iters = setup BiCGStab iterations,

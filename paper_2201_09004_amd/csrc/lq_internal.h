@@ -99,7 +99,7 @@ struct MgHier {
   void *Ahat64 = nullptr, *Ahat32 = nullptr;
   Geom gc{};  // shape of coarse vectors: Vh = K * Vc / 2 pseudo-sites per coarse parity
   double coarse_tol = 0.1;
-  int coarse_maxiter = 100, nu_post = 4, gcr_kmax = 8;
+  int coarse_maxiter = 100, nu_post = 4, gcr_kmax = 8, nu_pre = 0;
   double setup_seconds = 0;
   int setup_iters = 0;
   MgGeom geom() const { return MgGeom{Vc, B, nv, K, fine, nbr, face, cpar, cmap, csite}; }

@@ -738,6 +738,8 @@ int fgcr_mixed(Blas& bl, const Geom& g, const OpFn& M_hi, const OpFn& M_lo, cons
 // even-odd system M_hat e_e = bhat_e(r') (t = residual, u = M_hat t with
 // <u, t> and |u|^2 fused into the stencil, e_e += omega t, t -= omega u,
 // omega = <u, t> / |u|^2 per column), then e += the reconstructed correction.
+// With nu_pre > 0 the same smoother first acts on r, and the coarse level
+// restricts r - D e_pre (e_pre is kept in the correction).
 struct MgCycle {
   OpEnv& env;
   const MgHier& h;
@@ -745,6 +747,7 @@ struct MgCycle {
   int n;
   Vec r32, e32, t32, bc, xc, be, xe, to, ue, tmp64, tmp32;
   Vec she, sre, sue, sto, sde;  // smoother: even correction, residual, M_hat residual; odd temporary; full correction
+  Vec spre;                     // pre-smoothing correction (nu_pre > 0)
   Blas blc, ble;
   DBuf red;
   int tiles = 0;
@@ -774,6 +777,10 @@ struct MgCycle {
     sue = make_vec(g, 32, 12, n, 1, 0, s);
     sto = make_vec(g, 32, 12, n, 1, 1, s);
     sde = make_vec(g, 32, 12, n, 2, 0, s);
+    if (h.nu_pre > 0) {
+      spre = make_vec(g, 32, 12, n, 2, 0, s);
+      if (!spre.ok()) return fail(LQ_ENOMEM, "multigrid cycle buffers");
+    }
     tiles = (g.Vh + 63) / 64;
     red = DBuf(sizeof(double) * 4 * (size_t)tiles * n, s);
     if ((fp64_io && (!r32.ok() || !e32.ok())) || !t32.ok() || !bc.ok() || !xc.ok() || !be.ok() || !xe.ok() ||
@@ -789,6 +796,20 @@ struct MgCycle {
     if (!e) e = blas_prepare(env.ctx, ble, g, 1, n, s);
     return e;
   }
+  // sde = the correction of nu minimal-residual steps on the even-odd system
+  // for the full-lattice residual res (zero start; res is left unchanged)
+  int smooth(Vec& res, int nu) {
+    int e = 0;
+    if ((e = tm_schur_source(env, sre, res)) || (e = vec_zero(she))) return e;
+    for (int k = 0; k < nu; ++k) {
+      if ((e = tm_schur(env, 32, sue, sre, sto, 2, red.as<double>()))) return e;
+      if (launch_scalar(SC_BICG_OMEGA, red.as<double>(), tiles, n, st.d(), env.s)) return fail(LQ_EDEVICE, "scalar");
+      if ((e = ble.op(OP_AXPY, &sre, &she, nullptr, nullptr, nullptr, st.d(), ST_OMEGA, ST_OMEGA))) return e;
+      if (k + 1 < nu && (e = ble.op(OP_AXMY, &sue, &sre, nullptr, nullptr, nullptr, st.d(), ST_OMEGA, ST_OMEGA)))
+        return e;
+    }
+    return tm_schur_reconstruct(env, sde, she, res);
+  }
   // z = K r; r and z in FP32 are used in place, FP64 ones are converted
   int operator()(Vec& z, Vec& r) {
     int e = 0;
@@ -796,8 +817,15 @@ struct MgCycle {
     if (r.prec != 32 && (e = vec_copy(r32, r))) return e;
     Vec& rin = r.prec == 32 ? r : r32;
     Vec& ev = z.prec == 32 ? z : e32;
+    // optional pre-smoothing: its correction e_pre, and the coarse level sees r - D e_pre
+    Vec* res = &rin;
+    if (h.nu_pre > 0) {
+      if ((e = smooth(rin, h.nu_pre)) || (e = vec_copy(spre, sde))) return e;
+      if ((e = wilson_D(env, 32, t32, spre, false)) || (e = bl.op(OP_XMY_NORM, &rin, &t32))) return e;
+      res = &t32;
+    }
     // coarse solve on the even aggregates: (1 - A_ee^-1 D_eo A_oo^-1 D_oe) x_e = bhat_e
-    if ((e = mg_restrict(env, h, rin, bc)) || (e = mg_schur_source(env, h, be, to, ue, bc)) || (e = vec_zero(xe)))
+    if ((e = mg_restrict(env, h, *res, bc)) || (e = mg_schur_source(env, h, be, to, ue, bc)) || (e = vec_zero(xe)))
       return e;
     OpFn S = [&](Vec& o, const Vec& i) {
       Vec t = view(i.prec == 64 ? tmp64 : tmp32, 0, i.ncol);
@@ -808,19 +836,10 @@ struct MgCycle {
     if (rc != LQ_OK && rc != LQ_ENOCONV) return rc;
     if ((e = mg_schur_reconstruct(env, h, xc, xe, to))) return e;
     if ((e = mg_prolong(env, h, xc, ev))) return e;
-    // fine-level smoothing on the residual of the coarse correction, on the even-odd system
+    if (h.nu_pre > 0 && (e = bl.opi(OP_AXPY, &spre, &ev, nullptr, 1.0))) return e;
+    // fine-level smoothing on the residual of the correction so far, on the even-odd system
     if ((e = wilson_D(env, 32, t32, ev, false)) || (e = bl.op(OP_XMY_NORM, &rin, &t32))) return e;
-    if ((e = tm_schur_source(env, sre, t32)) || (e = vec_zero(she))) return e;
-    for (int k = 0; k < h.nu_post; ++k) {
-      if ((e = tm_schur(env, 32, sue, sre, sto, 2, red.as<double>()))) return e;
-      if (launch_scalar(SC_BICG_OMEGA, red.as<double>(), tiles, n, st.d(), env.s)) return fail(LQ_EDEVICE, "scalar");
-      if ((e = ble.op(OP_AXPY, &sre, &she, nullptr, nullptr, nullptr, st.d(), ST_OMEGA, ST_OMEGA))) return e;
-      if (k + 1 < h.nu_post &&
-          (e = ble.op(OP_AXMY, &sue, &sre, nullptr, nullptr, nullptr, st.d(), ST_OMEGA, ST_OMEGA)))
-        return e;
-    }
-    if ((e = tm_schur_reconstruct(env, sde, she, t32)) || (e = bl.opi(OP_AXPY, &sde, &ev, nullptr, 1.0)))
-      return e;
+    if ((e = smooth(t32, h.nu_post)) || (e = bl.opi(OP_AXPY, &sde, &ev, nullptr, 1.0))) return e;
     ++cycles;
     return z.prec == 32 ? 0 : vec_copy(z, e32);
   }
@@ -1889,6 +1908,8 @@ int mg_setup(lq_ctx* c, const lq_action* act, lq_field* f, const lq_mg_params* m
   const Geom& g = f->g;
   const int nv = mp->n_vec > 0 ? mp->n_vec : 30;
   if (nv % 6 != 0 || nv > 30) return fail(LQ_EINVAL, "n_vec must be 6, 12, 18, 24 or 30");
+  if (mp->nu_pre < 0 || mp->nu_pre > 16 || mp->nu_post < 0 || mp->nu_post > 16 || mp->reserved != 0)
+    return fail(LQ_EINVAL, "nu_pre and nu_post must be in [0, 16], reserved 0");
   for (int mu = 0; mu < 4; ++mu) {
     const int b = mp->block[mu];
     if (b < 2 || g.L[mu] % b != 0 || (g.L[mu] / b) % 2 != 0)
@@ -1922,6 +1943,7 @@ int mg_setup(lq_ctx* c, const lq_action* act, lq_field* f, const lq_mg_params* m
   h->coarse_maxiter = mp->coarse_maxiter > 0 ? mp->coarse_maxiter : 100;
   h->nu_post = mp->nu_post > 0 ? mp->nu_post : 4;
   h->gcr_kmax = mp->gcr_kmax > 0 ? mp->gcr_kmax : 8;
+  h->nu_pre = mp->nu_pre > 0 ? mp->nu_pre : 0;
   if ((e = mg_init_maps(*h, g, mp->block, nv)) || (e = mg_build(env, *h, w))) {
     mg_release(h);
     return e;

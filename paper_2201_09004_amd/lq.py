@@ -62,7 +62,8 @@ class lq_mg_params(C.Structure):
     _fields_ = [("block", C.c_int32 * 4), ("n_vec", C.c_int32), ("setup_passes", C.c_int32),
                 ("setup_maxiter", C.c_int32), ("coarse_maxiter", C.c_int32), ("setup_tol", C.c_double),
                 ("coarse_tol", C.c_double), ("seed", C.c_uint64), ("null_vecs", C.POINTER(C.c_double)),
-                ("nu_post", C.c_int32), ("gcr_kmax", C.c_int32)]
+                ("nu_post", C.c_int32), ("gcr_kmax", C.c_int32), ("nu_pre", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class lq_stats(C.Structure):
@@ -306,10 +307,10 @@ LQ_MG_RESTRICT, LQ_MG_PROLONG, LQ_MG_COARSE = 0, 1, 2
 
 
 def mg_params(block=(4, 4, 4, 4), n_vec=30, setup_passes=0, setup_maxiter=0, setup_tol=0.0, coarse_tol=0.0,
-              coarse_maxiter=0, nu_post=0, gcr_kmax=0, seed=1, null_vecs=None):
+              coarse_maxiter=0, nu_post=0, gcr_kmax=0, seed=1, null_vecs=None, nu_pre=0):
     p = lq_mg_params(n_vec=n_vec, setup_passes=setup_passes, setup_maxiter=setup_maxiter,
                      coarse_maxiter=coarse_maxiter, setup_tol=setup_tol, coarse_tol=coarse_tol, seed=seed,
-                     nu_post=nu_post, gcr_kmax=gcr_kmax)
+                     nu_post=nu_post, gcr_kmax=gcr_kmax, nu_pre=nu_pre)
     p.block[:] = list(block)
     if null_vecs is not None:
         arr = np.ascontiguousarray(null_vecs, dtype=np.complex128)

@@ -58,7 +58,7 @@ def test_struct_layouts_match_header(lib):
     assert C.sizeof(L.lq_geom) == 20
     assert C.sizeof(L.lq_action) == 80
     assert C.sizeof(L.lq_stats) == 48
-    assert C.sizeof(L.lq_mg_params) == 72
+    assert C.sizeof(L.lq_mg_params) == 80
 
 
 def test_struct_layouts_match_the_c_compiler(lib, tmp_path):

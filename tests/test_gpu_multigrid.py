@@ -70,10 +70,12 @@ def test_transfers_and_coarse_operator_match_oracle(ctx, Lx, block, nv):
         L.lq_field_free(f)
 
 
-def test_multigrid_solve_meets_oracle_residual(ctx):
+@pytest.mark.parametrize("nu_pre", [0, 2])
+def test_multigrid_solve_meets_oracle_residual(ctx, nu_pre):
     """Setup from random vectors (two inverse-iteration passes), then GCR with
-    one V-cycle per direction: 1e-10 with the oracle operator on 12 point
-    sources, the same solution as the even-odd BiCGStab."""
+    one V-cycle per direction (post-smoothing only, or pre- and post-smoothing):
+    1e-10 with the oracle operator on 12 point sources, the same solution as the
+    even-odd BiCGStab."""
     Lx = (8, 8, 8, 8)
     U = synth.su3_field(Lx, 0.2, 605)
     m, csw, mu = -0.0695, 1.0509, 0.01
@@ -81,7 +83,7 @@ def test_multigrid_solve_meets_oracle_residual(ctx):
     act = L.action(L.LQ_TM_CLOVER, m=m, mu=mu, c_sw=csw)
     b = synth.point_sources(Lx)
     try:
-        st = L.lq_mg_setup(ctx, act, f, L.mg_params(block=(4, 4, 4, 4), n_vec=12, seed=7))
+        st = L.lq_mg_setup(ctx, act, f, L.mg_params(block=(4, 4, 4, 4), n_vec=12, seed=7, nu_pre=nu_pre))
         print("setup", st)
         x, sx = L.lq_solve(ctx, act, f, L.params(tol=1e-10, solver=3, maxiter=300), b)
         print("multigrid", sx)
@@ -111,6 +113,9 @@ def test_multigrid_errors(ctx):
             with pytest.raises(L.LqError) as e:
                 L.lq_mg_setup(ctx, act, f, L.mg_params(block=block, n_vec=nv))
             assert e.value.code == L.LQ_EINVAL, (block, nv)
+        with pytest.raises(L.LqError) as e:
+            L.lq_mg_setup(ctx, act, f, L.mg_params(block=(2, 2, 2, 2), n_vec=6, nu_pre=17))
+        assert e.value.code == L.LQ_EINVAL
         L.lq_mg_setup(ctx, act, f, L.mg_params(block=(2, 2, 2, 2), n_vec=6, setup_maxiter=20))
         other = L.action(L.LQ_TM_CLOVER, m=-0.1, mu=0.1, c_sw=1.0)
         with pytest.raises(L.LqError) as e:
