@@ -545,7 +545,7 @@ def bench_hisq(args, L, torch):
     del V_d, W_d
     torch.cuda.empty_cache()
     act = L.action(L.LQ_HISQ, m=HISQ_MASSES[0])
-    prm = L.params(tol=1e-10, sloppy_bits=args.hisq_sloppy, masses=HISQ_MASSES)
+    prm = L.params(tol=1e-10, sloppy_bits=args.hisq_sloppy, masses=HISQ_MASSES, reliable_delta=args.delta)
     x_d = torch.zeros((len(HISQ_MASSES),) + tuple(b_d.shape), dtype=b_d.dtype, device=dev)
     for _ in range(args.warmup):
         _, st = L.lq_solve(ctx, act, field, prm, b_d, x_d)
@@ -1067,7 +1067,7 @@ def main():
     ap.add_argument("--no-mg", action="store_true", help="skip the multigrid propagator beside the bench line (tm)")
     ap.add_argument("--hisq-sloppy", type=int, default=16, choices=(16, 32), help="refinement storage (hisq)")
     ap.add_argument("--recon12", type=int, default=0)
-    ap.add_argument("--delta", type=float, default=0.0, help="reliable-update threshold (tm; 0: the library default 0.1)")
+    ap.add_argument("--delta", type=float, default=0.0, help="reliable-update threshold (tm, hisq; 0: the library default 0.1)")
     ap.add_argument("--serve-requests", type=int, default=256, help="requests per arrival rate (serve)")
     ap.add_argument("--serve-rates", default="0.5,0.8,0.95", help="arrival rates as fractions of capacity (serve)")
     ap.add_argument("--serve-capacity", type=float, default=0.0,
