@@ -63,14 +63,21 @@ using OpFn = std::function<int(Vec& out, const Vec& in)>;
 // active columns are due.  One update then serves every column.
 struct UpdateRule {
   int due = 0, active = 0;
+  int conv = 0;        // columns whose iterated residual is below their target
+  bool drop = false;   // a column dropped by delta^2 since its last update
   bool now = false;
   void column(double rr, double maxrr, double tol2bb, double delta) {
     ++active;
     const double d2 = delta * delta;
+    if (rr < tol2bb) ++conv;
+    if (rr < d2 * d2 * maxrr) drop = true;
     if (rr < tol2bb || rr < d2 * d2 * maxrr) now = true;
     else if (rr < d2 * maxrr) ++due;
   }
   bool fire() const { return now || (active > 0 && 2 * due >= active); }
+  // the update is due only because a few columns may have converged: checking
+  // those columns alone is enough
+  bool converged_few() const { return conv > 0 && !drop && 2 * due < active && 4 * conv <= active; }
 };
 
 // Iterations until a column's squared residual rr reaches the next threshold

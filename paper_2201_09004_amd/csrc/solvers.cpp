@@ -281,7 +281,40 @@ int cg_mixed(Blas& bl, const Geom& g, const OpFn& A_hi, const OpFn& A_lo, int pl
     }
     for (int c = 0; c < na; ++c) rr_chk[c] = st.h(c, ST_RR);
     since = 0;
-    if (update || it == maxiter - 1) {
+    if (update && rule.converged_few() && it < maxiter - 1) {
+      // Only a few columns are below their targets: fold every column's sloppy
+      // updates into x, move those columns to slots [0, m) and recompute the
+      // FP64 residual of these alone; the others keep iterating untouched.
+      ++cnt.reliable;
+      if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, na, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
+      if ((e = vec_zero(xsv))) return e;
+      dirty = false;
+      int m = 0;
+      for (int c = 0; c < na; ++c)
+        if (st.h(c, ST_RR) < tol[c] * tol[c] * bb[c]) {
+          if ((e = cm.swap(c, m))) return e;
+          ++m;
+        }
+      if ((e = st.push(na))) return e;
+      if (cp && (e = cp->upload())) return e;
+      {
+        Vec qv = view(q64, 0, m), xv = view(x, 0, m), bv = view(b, 0, m), rv = view(r, 0, m), rsm = view(rs, 0, m);
+        if ((e = A_hi(qv, xv)) || (e = bl.op(OP_XMY_NORM, &bv, &qv)) || (e = vec_copy(rv, qv))) return e;
+        if (launch_scalar(SC_SET_RR, bl.partial, bl.gridx, m, st.d(), s)) return fail(LQ_EDEVICE, "scalar");
+        if ((e = vec_copy(rsm, rv))) return e;
+      }
+      if ((e = st.pull(na))) return e;
+      for (int c = 0; c < m; ++c) {
+        const double rr = st.h(c, ST_RR);
+        if (!std::isfinite(rr)) return fail(LQ_ENUMERIC, "NaN/Inf in the true residual");
+        maxrr[c] = rr_chk[c] = rr;
+        if (rr <= tol[c] * tol[c] * bb[c]) {
+          st.h(c, ST_ACTIVE) = 0.0;
+          st.h(c, ST_BETA) = 0.0;
+        }
+      }
+      if ((e = compact())) return e;
+    } else if (update || it == maxiter - 1) {
       ++cnt.reliable;
       if ((e = launch_axpy_mixed(x.f, 64, xs.f, plo, nc, na, npar, g.Vh, s))) return fail(LQ_EDEVICE, "axpy");
       if ((e = vec_zero(xsv))) return e;
